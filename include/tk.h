@@ -1,0 +1,225 @@
+/*
+ * tk.h - C ABI of the Tucker-compressed S-model kinetic step for MI355X.
+ *
+ * One explicit first-order upwind finite-volume step of the tensorised
+ * discrete velocity method of Chikitkin, Kornev and Titarev ("Numerical
+ * solution of the Boltzmann equation with S-model collision integral using
+ * tensor decompositions"): every cell's distribution function on an N^3
+ * Cartesian velocity grid is a Tucker tensor (Section "Tensor
+ * decompositions"), and a step is Alg. 1 (boundary values, face fluxes of
+ * eq. exact-flux, the S-model collision term of Alg. 2 / eq.
+ * shakhov_integral, explicit Euler of eq. expl-scheme-final) followed by
+ * Tucker rounding (Op4, truncated HOSVD) back to a tolerance or rank cap.
+ *
+ * Conventions
+ *  - Every call returns tk_status: TK_OK (0), TK_PENDING (1) or a negative
+ *    error.  tk_last_error() returns the message of the last error raised
+ *    on a context.  No C++ exception crosses this interface.
+ *  - Host pointers passed in are only read during the call: inputs are
+ *    copied before return and may be freed by the caller afterwards.
+ *  - Outputs go to caller-allocated host buffers of the documented size.
+ *  - Handles belong to the caller until the matching *_destroy call.  A
+ *    state keeps a reference to its mesh: destroy states before meshes and
+ *    everything before the context.
+ *  - Calls on one context are serialised by the context.  The tk_serve_*
+ *    calls are thread-safe.
+ *  - All device work runs on the context's HIP stream.
+ *
+ * Physical units: R_g and m are parameters; the workloads use R_g = 1/2,
+ * m = 1, so 2 R_g T = T.  Viscosity mu(T) = (Kn/2) T^omega, collision
+ * frequency nu = p / mu with p = m n R_g T (Section "Mathematical model";
+ * the nondimensional form of mu is this library's reading).
+ */
+#ifndef TK_H
+#define TK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tk_status;
+#define TK_OK 0
+#define TK_PENDING 1
+#define TK_EINVAL (-1)   /* bad argument, shape or mesh                     */
+#define TK_ENOMEM (-2)   /* does not fit the memory budget / device memory   */
+#define TK_ENUMERIC (-3) /* n <= 0, T <= 0 or a non-finite value in a cell   */
+#define TK_EDEVICE (-4)  /* HIP runtime or kernel launch failure             */
+#define TK_EBUSY (-5)    /* server stopped or queue closed                   */
+#define TK_ENOTFOUND (-6)/* unknown ticket                                   */
+
+typedef struct tk_ctx tk_ctx;
+typedef struct tk_mesh tk_mesh;
+typedef struct tk_state tk_state;
+typedef struct tk_server tk_server;
+
+/* Boundary kinds (Section "Mathematical model": free stream, diffuse wall,
+ * symmetry plane; plus zero-gradient outflow).                            */
+enum { TK_BC_SYM = 0, TK_BC_INFLOW = 1, TK_BC_OUTFLOW = 2, TK_BC_WALL = 3 };
+
+typedef struct {
+  int32_t kind;   /* TK_BC_*                                               */
+  double n;       /* free-stream density (TK_BC_INFLOW)                    */
+  double u[3];    /* free-stream velocity (TK_BC_INFLOW)                   */
+  double T;       /* free-stream temperature (TK_BC_INFLOW)                */
+  double T_w;     /* wall temperature (TK_BC_WALL)                         */
+} tk_bc;
+
+/* Hexahedral mesh in the form the paper's mesh reader stores it (Section
+ * "Implementation"; eq. ode_system): per face the two cells, unit normal
+ * and area; per cell the volume.  A boundary face has face_right = -(b+1)
+ * with b an index into bc[], its left cell is the interior cell and its
+ * normal points out of the domain.  Periodic boundaries are interior
+ * faces.  Every cell must have at most 6 faces and be closed
+ * (|sum_l s_l A_l e_l| <= 1e-12 sum_l A_l), otherwise TK_EINVAL.
+ * Symmetry and wall boundaries must lie on coordinate-axis planes.        */
+typedef struct {
+  int32_t n_cells;
+  int32_t n_faces;
+  const int32_t* face_left;    /* [n_faces]                               */
+  const int32_t* face_right;   /* [n_faces]                               */
+  const double* face_normal;   /* [n_faces][3], unit, left -> right       */
+  const double* face_area;     /* [n_faces]                               */
+  const double* cell_volume;   /* [n_cells]                               */
+  const double* cell_center;   /* [n_cells][3], may be NULL               */
+  int32_t n_bc;
+  const tk_bc* bc;             /* [n_bc]                                  */
+} tk_mesh_desc;
+
+enum { TK_FP64 = 0, TK_MIXED = 1 };
+
+/* Solver parameters of one instance.  Velocity grid (Section "Discrete
+ * velocity method"): N uniform nodes per axis on [-xi_max, xi_max] with
+ * the end points included, quadrature weight dxi^3.                       */
+typedef struct {
+  int32_t N;          /* 16, 24, 32 or 48                                  */
+  double xi_max;
+  double R_g, m;      /* gas constant, molecular mass                      */
+  double Pr;          /* Prandtl number (2/3 for a monatomic gas)          */
+  double omega;       /* viscosity exponent                                */
+  double Kn;          /* mu(T) = (Kn/2) T^omega                            */
+  double tol;         /* rounding tolerance eps (Op4)                      */
+  int32_t rank_cap;   /* 1 .. 16                                           */
+  double cfl;         /* dt = cfl / max_i (D_i + nu_i^0), see tk_state_dt  */
+  int32_t precision;  /* TK_FP64 or TK_MIXED                               */
+} tk_params;
+
+/* A Tucker tensor A(i1,i2,i3) = sum G(k1,k2,k3) U1(i1,k1) U2(i2,k2) U3(i3,k3)
+ * with N x r_a factors stored column-major (U_a[i + N k]) and the core
+ * column-major (G[k1 + r1 (k2 + r2 k3)]).  Caller-owned buffers; on output
+ * core must hold rank_cap^3 and each U[a] N * rank_cap doubles.           */
+typedef struct {
+  int32_t N;
+  int32_t r[3];
+  double* core;
+  double* U[3];
+} tk_tucker;
+
+/* ---- context ------------------------------------------------------------ */
+/* device: HIP device ordinal, or -1 for a host-only context that can load
+ * and validate meshes but runs no device work (state creation and rounding
+ * then return TK_EDEVICE).  hbm_budget: bytes the library may allocate
+ * (0 = 90% of free device memory).  hip_stream: a hipStream_t to run on
+ * (NULL = the library creates one at default priority).  TK_EDEVICE if the
+ * device is not available.                                                */
+tk_status tk_ctx_create(int32_t device, size_t hbm_budget, void* hip_stream, tk_ctx** out);
+tk_status tk_ctx_destroy(tk_ctx* ctx);
+const char* tk_last_error(const tk_ctx* ctx);
+tk_status tk_sync(tk_ctx* ctx);
+/* Per-kernel timing with HIP events recorded on the context stream around
+ * every launch of the named kernel family while enabled.                  */
+tk_status tk_prof_enable(tk_ctx* ctx, int32_t on);
+tk_status tk_prof_get(tk_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
+tk_status tk_prof_reset(tk_ctx* ctx);
+
+/* ---- mesh ------------------------------------------------------------------ */
+tk_status tk_mesh_load(tk_ctx* ctx, const tk_mesh_desc* desc, tk_mesh** out);
+tk_status tk_mesh_destroy(tk_mesh* mesh);
+
+/* ---- state -------------------------------------------------------------- */
+/* Rank-1 Maxwellian per cell from macro[n_cells][5] = (n, u1, u2, u3, T)
+ * (Section "Tensorized discrete velocity method": the Maxwellian is the
+ * product of three 1-D functions).  Computes the face data and dt.
+ * TK_ENUMERIC if some n <= 0 or T <= 0; TK_ENOMEM if it does not fit.    */
+tk_status tk_state_init(tk_ctx* ctx, const tk_mesh* mesh, const tk_params* params,
+                        const double* macro, tk_state** out);
+/* Several independent instances advanced together (same N and precision;
+ * other parameters per instance).  Cells are numbered instance after
+ * instance in the order given.                                            */
+tk_status tk_state_init_batch(tk_ctx* ctx, int32_t count, const tk_mesh* const* meshes,
+                              const tk_params* params, const double* const* macros,
+                              tk_state** out);
+tk_status tk_state_destroy(tk_state* st);
+/* Number of cells, instances, and the dt of instance `inst`.               */
+tk_status tk_state_info(const tk_state* st, int32_t* n_cells, int32_t* n_instances);
+tk_status tk_state_dt(const tk_state* st, int32_t inst, double* dt);
+
+/* Macroparameters of every cell, out[n_cells][8] = (n, u1, u2, u3, T, q1,
+ * q2, q3), computed on the device in FP64 from the Tucker state (Alg. 2
+ * steps 1-9 by Op5 convolutions).  Blocking.                              */
+tk_status tk_moments(tk_state* st, double* out);
+
+/* Advance nsteps explicit steps (Alg. 1 with one rounding per cell per
+ * step).  Enqueued on the context stream and waited for.  residual, if not
+ * NULL, receives per instance max(||dn||/||n||, ||dT||/||T||) over the
+ * last step (cell-volume weighted 2-norms).  TK_ENUMERIC if a cell's n or
+ * T became non-positive or non-finite (the state is left as computed).    */
+tk_status tk_step(tk_state* st, int32_t nsteps, double* residual);
+/* Enqueue nsteps steps without waiting (no residual, no numeric check).   */
+tk_status tk_step_async(tk_state* st, int32_t nsteps);
+
+/* Rank histogram (hist[0..16], ranks are max over modes) and mean
+ * compression ratio C = (r1 r2 r3 + N (r1 + r2 + r3)) / N^3 (Section "Test
+ * problem").                                                              */
+tk_status tk_state_ranks(tk_state* st, int32_t* ranks /* [n_cells][3] or NULL */,
+                         double* mean_compression);
+
+/* Copy one cell's Tucker state out (columns beyond the ranks are not
+ * written).                                                               */
+tk_status tk_state_export(tk_state* st, int32_t cell, tk_tucker* out);
+
+/* Test hook for Op4: round `count` Tucker tensors (same N, ranks <= N)
+ * with tolerance tol and rank cap `cap` by truncated HOSVD on the device,
+ * FP64 throughout.  TK_EINVAL if a rank exceeds N.                        */
+tk_status tk_round_tucker(tk_ctx* ctx, int32_t count, const tk_tucker* in, double tol,
+                          int32_t cap, tk_tucker* out);
+
+/* ---- plain full-tensor comparator -------------------------------------- */
+/* The same step with N^3 values stored per cell and no rounding (the
+ * paper's baseline discrete velocity method).  Precision TK_FP64 stores
+ * doubles, TK_MIXED stores floats (FP64 moments).                        */
+tk_status tk_plain_init(tk_ctx* ctx, const tk_mesh* mesh, const tk_params* params,
+                        const double* macro, tk_state** out);
+
+/* ---- serving --------------------------------------------------------------- */
+typedef struct {
+  tk_mesh_desc mesh;
+  tk_params params;
+  const double* macro;   /* [n_cells][5]                                   */
+  int32_t max_steps;
+  double residual_tol;   /* stop when residual < residual_tol             */
+} tk_request;
+
+typedef struct {
+  tk_status status;      /* TK_PENDING while queued or running             */
+  int32_t steps;
+  double residual;
+  double t_arrive, t_admit, t_done;  /* seconds on the server's clock      */
+  double* macro_out;     /* caller buffer [n_cells][8], filled when done, may be NULL */
+} tk_result;
+
+/* Continuous batching over one device: admitted requests share the step
+ * launches of their N-bucket, states stay resident; admission by memory
+ * against hbm_budget.                                                     */
+tk_status tk_serve_create(tk_ctx* ctx, size_t hbm_budget, tk_server** out);
+/* Never blocks; TK_ENOMEM only for a request that could never fit.       */
+tk_status tk_serve_submit(tk_server* srv, const tk_request* req, uint64_t* ticket);
+tk_status tk_serve_poll(tk_server* srv, uint64_t ticket, tk_result* res);
+tk_status tk_serve_destroy(tk_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TK_H */

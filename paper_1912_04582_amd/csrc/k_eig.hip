@@ -1,0 +1,251 @@
+// Symmetric eigen-decomposition of the mode Gram matrices and the
+// truncation rule of the rounding (Op4 / Op1: ||A - B||_F <= eps ||A||_F).
+//
+// One wavefront per N x N matrix runs cyclic Jacobi with the parallel
+// round-robin ordering (N/2 disjoint rotations per round, N-1 rounds per
+// sweep) in LDS, until no off-diagonal element exceeds both
+// 1e-15 sqrt(|a_pp a_qq|) and 1e-18 trace.  Eigenvalues of G_a are the
+// squared singular values of the mode-a unfolding (eq. svd).  The kept rank
+// is the smallest r >= 1 whose discarded eigenvalues sum to at most
+// eps^2 trace / 3, capped; the kept eigenvectors (sorted by decreasing
+// eigenvalue) become the new factor, each column's largest-magnitude entry
+// made positive.
+//
+// Accuracy: a Gram matrix formed in FP64 carries errors of order
+// eps ||A||^2, which move the kept subspace by eps sigma_1^2 / sigma_r.  The
+// FP64 path therefore runs a second pass: the unfolding is rotated by the
+// first basis W, B = W^T A_(a), the Gram of B (whose errors scale with its
+// row norms) is diagonalised again and the final vectors are W V'.  For
+// that pass the kernel takes the first basis as `Win`; with `Wout` it
+// returns the full sorted basis instead of the truncated factor.
+#include "tk_internal.h"
+
+namespace tk {
+
+namespace {
+
+template <int N>
+__global__ __launch_bounds__(64) void k_eig(const double* Gm, const int* inst, const InstParams* ip, int c0,
+                                            double tol_o, int cap_o, int CS, double* fac_n, int* rank_n,
+                                            const double* Win, double* Wout) {
+  constexpr int LD = N + 1;
+  constexpr int NH = N / 2;
+  constexpr int NBLK = NH * (NH + 1) / 2;
+  __shared__ double A[N * LD];
+  __shared__ double V[N * LD];
+  __shared__ double cs[NH], sn[NH], tt[NH];
+  __shared__ int pp[NH], qq[NH];
+  __shared__ int bi_[NBLK], bj_[NBLK];
+  __shared__ int order[N];
+  __shared__ int any;
+  __shared__ double s_tot;
+  __shared__ int s_rank;
+  const int m = blockIdx.x;
+  const int cl = m / 3, mode = m % 3;
+  const int cell = c0 + cl;
+  const int lane = threadIdx.x;
+  const double* g = Gm + (size_t)m * N * N;
+  for (int o = lane; o < N * N; o += 64) {
+    const int i = o / N, j = o % N;
+    A[i * LD + j] = g[o];
+    V[i * LD + j] = (i == j) ? 1.0 : 0.0;
+  }
+  for (int b = lane; b < NBLK; b += 64) {
+    // enumerate (I, J), I <= J
+    int I = 0, rem = b;
+    while (rem >= NH - I) { rem -= NH - I; ++I; }
+    bi_[b] = I;
+    bj_[b] = I + rem;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    double t = 0.0;
+    for (int i = 0; i < N; ++i) t += A[i * LD + i];
+    s_tot = t;
+  }
+  __syncthreads();
+  const double abs_thr = 1e-18 * fabs(s_tot);
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (lane == 0) any = 0;
+    __syncthreads();
+    for (int r = 0; r < N - 1; ++r) {
+      if (lane < NH) {
+        int p, q;
+        if (lane == 0) {
+          p = 0;
+          q = 1 + r % (N - 1);
+        } else {
+          p = 1 + (r + lane) % (N - 1);
+          q = 1 + (r + N - 1 - lane) % (N - 1);
+        }
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double app = A[p * LD + p], aqq = A[q * LD + q], apq = A[p * LD + q];
+        double c = 1.0, s = 0.0, t = 0.0;
+        if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app * aqq)), abs_thr) && apq != 0.0) {
+          const double th = (aqq - app) / (2.0 * apq);
+          if (fabs(th) > 1e150) {
+            t = 0.5 / th;
+          } else {
+            t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          }
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+          any = 1;
+        }
+        pp[lane] = p; qq[lane] = q; cs[lane] = c; sn[lane] = s; tt[lane] = t;
+      }
+      __syncthreads();
+      for (int b = lane; b < NBLK; b += 64) {
+        const int I = bi_[b], J = bj_[b];
+        const int pI = pp[I], qI = qq[I], pJ = pp[J], qJ = qq[J];
+        if (I == J) {
+          const double t = tt[I];
+          if (t != 0.0) {
+            const double apq = A[pI * LD + qI];
+            A[pI * LD + pI] -= t * apq;
+            A[qI * LD + qI] += t * apq;
+            A[pI * LD + qI] = 0.0;
+            A[qI * LD + pI] = 0.0;
+          }
+        } else {
+          const double cI = cs[I], sI = sn[I], cJ = cs[J], sJ = sn[J];
+          const double a = A[pI * LD + pJ], bb = A[pI * LD + qJ];
+          const double cc = A[qI * LD + pJ], dd = A[qI * LD + qJ];
+          const double a1 = cJ * a - sJ * bb, b1 = sJ * a + cJ * bb;
+          const double c1 = cJ * cc - sJ * dd, d1 = sJ * cc + cJ * dd;
+          const double a2 = cI * a1 - sI * c1, c2 = sI * a1 + cI * c1;
+          const double b2 = cI * b1 - sI * d1, d2 = sI * b1 + cI * d1;
+          A[pI * LD + pJ] = a2; A[pJ * LD + pI] = a2;
+          A[pI * LD + qJ] = b2; A[qJ * LD + pI] = b2;
+          A[qI * LD + pJ] = c2; A[pJ * LD + qI] = c2;
+          A[qI * LD + qJ] = d2; A[qJ * LD + qI] = d2;
+        }
+      }
+      for (int it = lane; it < N * NH; it += 64) {
+        const int row = it % N, J = it / N;
+        const double c = cs[J], s = sn[J];
+        if (s == 0.0) continue;
+        const int p = pp[J], q = qq[J];
+        const double v1 = V[row * LD + p], v2 = V[row * LD + q];
+        V[row * LD + p] = c * v1 - s * v2;
+        V[row * LD + q] = s * v1 + c * v2;
+      }
+      __syncthreads();
+    }
+    if (!any) break;
+  }
+  // sort eigenvalues, descending (stable on ties); the identity order first so
+  // that every entry stays a valid index even if a value is not a number
+  if (lane < N) order[lane] = lane;
+  __syncthreads();
+  if (lane < N) {
+    const double li = A[lane * LD + lane];
+    int pos = 0;
+    for (int j = 0; j < N; ++j) {
+      const double lj = A[j * LD + j];
+      pos += (lj > li) || (lj == li && j < lane);
+    }
+    if (pos < N) order[pos] = lane;
+  }
+  __syncthreads();
+  if (Wout) {
+    // full sorted basis (premultiplied by Win when given), no truncation
+    double* out = Wout + (size_t)m * N * N;
+    for (int o = lane; o < N * N; o += 64) {
+      const int k = o / N, i = o % N, j = order[k];
+      double v;
+      if (Win) {
+        const double* w = Win + (size_t)m * N * N;
+        v = 0.0;
+        for (int t = 0; t < N; ++t) v += w[t * N + i] * V[t * LD + j];
+      } else {
+        v = V[i * LD + j];
+      }
+      out[o] = v;
+    }
+    return;
+  }
+  if (lane == 0) {
+    double tol = tol_o;
+    int cap = cap_o;
+    if (inst) {
+      const InstParams P = ip[inst[cell]];
+      tol = P.tol;
+      cap = P.cap;
+    }
+    double tot = 0.0;
+    for (int i = 0; i < N; ++i) tot += A[order[i] * LD + order[i]];
+    const double thr = tol * tol * tot / 3.0;
+    // smallest r >= 1 with sum_{k >= r} lambda_k <= thr
+    int r = N;
+    double tail = 0.0;
+    for (int k = N - 1; k >= 1; --k) {
+      tail += A[order[k] * LD + order[k]];
+      if (tail <= thr) r = k;
+      else break;
+    }
+    if (r > cap) r = cap;
+    if (r < 1) r = 1;
+    s_rank = r;
+    rank_n[3 * cell + mode] = r;
+  }
+  __syncthreads();
+  const int r = s_rank;
+  double* out = fac_n + ((size_t)cell * 3 + mode) * CS * N;
+  double* vec = A;  // the matrix is no longer needed: column scratch
+  for (int k = 0; k < CS; ++k) {
+    if (k < r) {
+      const int j = order[k];
+      for (int i = lane; i < N; i += 64) {
+        double v;
+        if (Win) {
+          const double* w = Win + (size_t)m * N * N;
+          v = 0.0;
+          for (int t = 0; t < N; ++t) v += w[t * N + i] * V[t * LD + j];
+        } else {
+          v = V[i * LD + j];
+        }
+        vec[i] = v;
+      }
+      __syncthreads();
+      // canonical sign: largest-magnitude entry positive (first on ties)
+      if (lane == 0) {
+        double best = -1.0;
+        int bi = 0;
+        for (int i = 0; i < N; ++i) {
+          const double v = fabs(vec[i]);
+          if (v > best) { best = v; bi = i; }
+        }
+        cs[0] = (vec[bi] < 0.0) ? -1.0 : 1.0;
+      }
+      __syncthreads();
+      const double sg = cs[0];
+      for (int i = lane; i < N; i += 64) out[k * N + i] = sg * vec[i];
+      __syncthreads();
+    } else {
+      for (int i = lane; i < N; i += 64) out[k * N + i] = 0.0;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
+                      double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
+                      const double* Win, double* Wout, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  dim3 grid(3 * count), blk(64);
+#define TK_EIG(NN) hipLaunchKernelGGL(k_eig<NN>, grid, blk, 0, s, G, inst, ip, c0, tol_override, cap_override, CS, \
+                                      fac_n, rank_n, Win, Wout)
+  switch (N) {
+    case 16: TK_EIG(16); break;
+    case 24: TK_EIG(24); break;
+    case 32: TK_EIG(32); break;
+    case 48: TK_EIG(48); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef TK_EIG
+  return hipGetLastError();
+}
+
+}  // namespace tk

@@ -1,0 +1,113 @@
+// Core of the rounded tensor: C = A x1 W1^T x2 W2^T x3 W3^T (the last step of
+// the truncated HOSVD, Op1/Op4), with W_a the kept eigenvectors of the mode
+// Gram matrices.  One workgroup per cell walks the mode-3 slices of A:
+// Q = W1^T A(:,:,i3), T = Q W2, then C(:,:,k3) += T W3(i3,k3).  FP64
+// accumulation whatever the storage type of A.
+#include "tk_internal.h"
+
+namespace tk {
+
+namespace {
+
+constexpr int kProjThreads = 256;
+
+template <int N, typename T>
+__global__ __launch_bounds__(kProjThreads) void k_project(const T* X, int c0, int CS, const double* fac_n,
+                                                         const int* rank_n, double* core_n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* sS = reinterpret_cast<double*>(smem_raw);  // N*N slice
+  double* sW = sS + N * N;                             // 3 * CS * N
+  double* sQ = sW + 3 * CS * N;                        // CS * N
+  double* sT = sQ + CS * N;                            // CS * CS
+  const int cl = blockIdx.x;
+  const int cell = c0 + cl;
+  const int tid = threadIdx.x;
+  const int r1 = rank_n[3 * cell], r2 = rank_n[3 * cell + 1], r3 = rank_n[3 * cell + 2];
+  for (int o = tid; o < 3 * CS * N; o += kProjThreads)
+    sW[o] = fac_n[(size_t)cell * 3 * CS * N + o];
+  constexpr int MAXC = kMaxCap * kMaxCap * kMaxCap / kProjThreads;
+  double acc[MAXC];
+#pragma unroll
+  for (int m = 0; m < MAXC; ++m) acc[m] = 0.0;
+  const int tot = r1 * r2 * r3;
+  const T* x = X + (size_t)cl * N * N * N;
+  const double* W1 = sW;
+  const double* W2 = sW + CS * N;
+  const double* W3 = sW + 2 * CS * N;
+  for (int i3 = 0; i3 < N; ++i3) {
+    __syncthreads();
+    for (int o = tid; o < N * N; o += kProjThreads) sS[o] = (double)x[(size_t)i3 * N * N + o];
+    __syncthreads();
+    // Q[k1][i2] = sum_i1 W1[k1][i1] S[i1 + N i2]
+    for (int o = tid; o < r1 * N; o += kProjThreads) {
+      const int i2 = o % N, k1 = o / N;
+      double s = 0.0;
+      for (int i1 = 0; i1 < N; ++i1) s += W1[k1 * N + i1] * sS[i1 + N * i2];
+      sQ[k1 * N + i2] = s;
+    }
+    __syncthreads();
+    // T[k1 + r1 k2] = sum_i2 Q[k1][i2] W2[k2][i2]
+    for (int o = tid; o < r1 * r2; o += kProjThreads) {
+      const int k1 = o % r1, k2 = o / r1;
+      double s = 0.0;
+      for (int i2 = 0; i2 < N; ++i2) s += sQ[k1 * N + i2] * W2[k2 * N + i2];
+      sT[o] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MAXC; ++m) {
+      const int o = tid + kProjThreads * m;
+      if (o < tot) {
+        const int k12 = o % (r1 * r2), k3 = o / (r1 * r2);
+        acc[m] += sT[k12] * W3[k3 * N + i3];
+      }
+    }
+  }
+  double* out = core_n + (size_t)cell * CS * CS * CS;
+  for (int o = tid; o < CS * CS * CS; o += kProjThreads) {
+    const int k1 = o % CS, t = o / CS, k2 = t % CS, k3 = t / CS;
+    if (k1 >= r1 || k2 >= r2 || k3 >= r3) out[o] = 0.0;
+  }
+#pragma unroll
+  for (int m = 0; m < MAXC; ++m) {
+    const int o = tid + kProjThreads * m;
+    if (o < tot) {
+      const int k1 = o % r1, t = o / r1, k2 = t % r2, k3 = t / r2;
+      out[k1 + CS * (k2 + CS * k3)] = acc[m];
+    }
+  }
+}
+
+template <int N, typename T>
+hipError_t launch_project_t(int count, const void* X, int c0, int CS, const double* fac_n, const int* rank_n,
+                            double* core_n, hipStream_t s) {
+  const size_t sh = sizeof(double) * (N * N + 3 * CS * N + CS * N + CS * CS);
+  hipLaunchKernelGGL((k_project<N, T>), dim3(count), dim3(kProjThreads), sh, s, (const T*)X, c0, CS, fac_n,
+                     rank_n, core_n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_project(int N, int count, const void* X, int mixed, int c0, int CS, const double* fac_n,
+                          const int* rank_n, double* core_n, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (mixed) {
+    switch (N) {
+      case 16: return launch_project_t<16, float>(count, X, c0, CS, fac_n, rank_n, core_n, s);
+      case 24: return launch_project_t<24, float>(count, X, c0, CS, fac_n, rank_n, core_n, s);
+      case 32: return launch_project_t<32, float>(count, X, c0, CS, fac_n, rank_n, core_n, s);
+      case 48: return launch_project_t<48, float>(count, X, c0, CS, fac_n, rank_n, core_n, s);
+    }
+  } else {
+    switch (N) {
+      case 16: return launch_project_t<16, double>(count, X, c0, CS, fac_n, rank_n, core_n, s);
+      case 24: return launch_project_t<24, double>(count, X, c0, CS, fac_n, rank_n, core_n, s);
+      case 32: return launch_project_t<32, double>(count, X, c0, CS, fac_n, rank_n, core_n, s);
+      case 48: return launch_project_t<48, double>(count, X, c0, CS, fac_n, rank_n, core_n, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tk

@@ -1,0 +1,886 @@
+// Host side of the tk library: contexts, meshes, states, the step driver
+// and the C ABI entry points (declared in tk.h).
+//
+// Mesh data follow the finite-volume form of the method (eq. ode_system):
+// per face its two cells, unit normal and area, per cell its volume.  Each
+// cell gets up to six face slots naming what lies on the far side and the
+// slot's outward orientation, with coefficient dt A / V.  The time step is
+// dt = cfl / max_i (D_i + nu_i^0), D_i = xi_max / (2 V_i) sum_l A_l ||e_l||_1,
+// the positivity bound of the explicit scheme (eq. expl-scheme-final),
+// with nu^0 taken from the initial macroparameters.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+
+#include "tk_internal.h"
+#include "tk_runtime.h"
+
+namespace tk {
+const char* kKernelNames[KID_COUNT] = {"moments", "expand", "gram", "eig", "project", "init",
+                                       "plain_moments", "plain_step", "residual"};
+}
+
+using namespace tk;
+
+// ---------------------------------------------------------------------------
+// context helpers
+
+tk_status ctx_fail(tk_ctx* ctx, tk_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+tk_status ctx_hip(tk_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return TK_OK;
+  return ctx_fail(ctx, e == hipErrorOutOfMemory ? TK_ENOMEM : TK_EDEVICE,
+                  std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* ctx_alloc(tk_ctx* ctx, size_t bytes, tk_status* st) {
+  *st = TK_OK;
+  if (bytes == 0) bytes = 8;
+  bytes = (bytes + 255) & ~size_t(255);
+  if (ctx->used + bytes > ctx->budget) {
+    *st = ctx_fail(ctx, TK_ENOMEM, "allocation of " + std::to_string(bytes) + " bytes exceeds the budget");
+    return nullptr;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    *st = ctx_hip(ctx, e, "hipMalloc");
+    return nullptr;
+  }
+  ctx->used += bytes;
+  ctx->sizes[p] = bytes;
+  return p;
+}
+
+void ctx_free(tk_ctx* ctx, void* p) {
+  if (!p) return;
+  auto it = ctx->sizes.find(p);
+  if (it != ctx->sizes.end()) {
+    ctx->used -= it->second;
+    ctx->sizes.erase(it);
+  }
+  (void)hipFree(p);
+}
+
+void prof_begin(tk_ctx* ctx, int kid, hipEvent_t* ev) {
+  *ev = nullptr;
+  if (!ctx->prof) return;
+  if (ctx->ev_pool.empty()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    ctx->ev_pool.push_back(e);
+  }
+  *ev = ctx->ev_pool.back();
+  ctx->ev_pool.pop_back();
+  (void)hipEventRecord(*ev, ctx->stream);
+  (void)kid;
+}
+
+void prof_end(tk_ctx* ctx, int kid, hipEvent_t start) {
+  if (!ctx->prof || !start) return;
+  hipEvent_t e;
+  if (ctx->ev_pool.empty()) {
+    if (hipEventCreate(&e) != hipSuccess) return;
+  } else {
+    e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+  }
+  (void)hipEventRecord(e, ctx->stream);
+  ctx->pending.push_back({kid, start, e});
+}
+
+void prof_harvest(tk_ctx* ctx) {
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->prof_ms[p.kid] += ms;
+      ctx->prof_n[p.kid] += 1;
+    }
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// mesh
+
+static tk_status mesh_build(tk_ctx* ctx, const tk_mesh_desc* d, tk_mesh* m) {
+  if (!d || d->n_cells <= 0 || d->n_faces <= 0 || !d->face_left || !d->face_right || !d->face_normal ||
+      !d->face_area || !d->cell_volume || d->n_bc < 0 || (d->n_bc > 0 && !d->bc))
+    return ctx_fail(ctx, TK_EINVAL, "mesh: missing arrays or empty mesh");
+  const int nc = d->n_cells, nf = d->n_faces;
+  m->n_cells = nc;
+  m->n_faces = nf;
+  m->volume.assign(d->cell_volume, d->cell_volume + nc);
+  m->bc.assign(d->bc, d->bc + d->n_bc);
+  for (int i = 0; i < nc; ++i)
+    if (!(m->volume[i] > 0.0) || !std::isfinite(m->volume[i]))
+      return ctx_fail(ctx, TK_EINVAL, "mesh: non-positive cell volume at cell " + std::to_string(i));
+  for (const tk_bc& b : m->bc)
+    if (b.kind < TK_BC_SYM || b.kind > TK_BC_WALL) return ctx_fail(ctx, TK_EINVAL, "mesh: unknown bc kind");
+  m->slot_nb.assign((size_t)nc * kSlots, -1);
+  m->slot_kind.assign((size_t)nc * kSlots, SK_NONE);
+  m->slot_axis.assign((size_t)nc * kSlots, 0);
+  m->slot_sig.assign((size_t)nc * kSlots, 1);
+  m->slot_area.assign((size_t)nc * kSlots, 0.0);
+  m->slot_l1.assign((size_t)nc * kSlots, 0.0);
+  std::vector<int> cnt(nc, 0);
+  std::vector<double> close((size_t)nc * 3, 0.0), asum(nc, 0.0);
+  auto add_slot = [&](int c, int nb, int8_t kind, const double* e, double sgn, double A) -> tk_status {
+    if (cnt[c] >= kSlots) return ctx_fail(ctx, TK_EINVAL, "mesh: cell " + std::to_string(c) + " has more than 6 faces");
+    int axis = -1, nz = 0;
+    for (int a = 0; a < 3; ++a)
+      if (e[a] != 0.0) { axis = a; ++nz; }
+    if (nz != 1 || std::fabs(std::fabs(e[axis]) - 1.0) > 1e-12)
+      return ctx_fail(ctx, TK_EINVAL, "mesh: face normals off the coordinate axes are not supported");
+    const int s = cnt[c]++;
+    const size_t k = (size_t)c * kSlots + s;
+    m->slot_nb[k] = nb;
+    m->slot_kind[k] = kind;
+    m->slot_axis[k] = (int8_t)axis;
+    m->slot_sig[k] = (int8_t)((sgn * e[axis]) > 0 ? 1 : -1);
+    m->slot_area[k] = A;
+    m->slot_l1[k] = A * (std::fabs(e[0]) + std::fabs(e[1]) + std::fabs(e[2]));
+    for (int a = 0; a < 3; ++a) close[3 * c + a] += sgn * A * e[a];
+    asum[c] += A;
+    return TK_OK;
+  };
+  for (int j = 0; j < nf; ++j) {
+    const int L = d->face_left[j], R = d->face_right[j];
+    const double* e = d->face_normal + 3 * (size_t)j;
+    const double A = d->face_area[j];
+    if (L < 0 || L >= nc) return ctx_fail(ctx, TK_EINVAL, "mesh: face_left out of range at face " + std::to_string(j));
+    if (!(A > 0.0) || !std::isfinite(A)) return ctx_fail(ctx, TK_EINVAL, "mesh: bad face area");
+    const double en = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    if (std::fabs(en - 1.0) > 1e-10) return ctx_fail(ctx, TK_EINVAL, "mesh: face normal is not unit length");
+    tk_status st;
+    if (R >= 0) {
+      if (R >= nc || R == L) return ctx_fail(ctx, TK_EINVAL, "mesh: face_right out of range");
+      if ((st = add_slot(L, R, SK_INTERIOR, e, 1.0, A)) != TK_OK) return st;
+      if ((st = add_slot(R, L, SK_INTERIOR, e, -1.0, A)) != TK_OK) return st;
+    } else {
+      const int b = -R - 1;
+      if (b >= (int)m->bc.size()) return ctx_fail(ctx, TK_EINVAL, "mesh: boundary index out of range");
+      int8_t kind = SK_NONE;
+      switch (m->bc[b].kind) {
+        case TK_BC_SYM: kind = SK_SYM; break;
+        case TK_BC_INFLOW: kind = SK_INFLOW; break;
+        case TK_BC_OUTFLOW: kind = SK_OUTFLOW; break;
+        case TK_BC_WALL: kind = SK_WALL; break;
+      }
+      if ((st = add_slot(L, b, kind, e, 1.0, A)) != TK_OK) return st;
+    }
+  }
+  for (int c = 0; c < nc; ++c) {
+    const double r = std::sqrt(close[3 * c] * close[3 * c] + close[3 * c + 1] * close[3 * c + 1] +
+                               close[3 * c + 2] * close[3 * c + 2]);
+    if (r > 1e-12 * asum[c]) return ctx_fail(ctx, TK_EINVAL, "mesh: cell " + std::to_string(c) + " is not closed");
+  }
+  return TK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// state
+
+static const int kSupportedN[] = {16, 24, 32, 48};
+
+static tk_status check_params(tk_ctx* ctx, const tk_params* p) {
+  bool okN = false;
+  for (int n : kSupportedN) okN |= (p->N == n);
+  if (!okN) return ctx_fail(ctx, TK_EINVAL, "params: N must be 16, 24, 32 or 48");
+  if (p->rank_cap < 1 || p->rank_cap > kMaxCap || p->rank_cap > p->N)
+    return ctx_fail(ctx, TK_EINVAL, "params: rank_cap must be in 1..16 and <= N");
+  if (!(p->xi_max > 0) || !(p->R_g > 0) || !(p->m > 0) || !(p->Kn > 0) || !(p->cfl > 0) || !(p->tol >= 0) ||
+      !(p->Pr > 0))
+    return ctx_fail(ctx, TK_EINVAL, "params: xi_max, R_g, m, Kn, cfl, Pr must be positive and tol >= 0");
+  if (p->precision != TK_FP64 && p->precision != TK_MIXED)
+    return ctx_fail(ctx, TK_EINVAL, "params: precision must be TK_FP64 or TK_MIXED");
+  if (p->precision == TK_FP64 && p->N == 48)
+    return ctx_fail(ctx, TK_EINVAL, "params: the FP64 path supports N <= 32");
+  return TK_OK;
+}
+
+static double collision_freq(const tk_params& p, double n, double T) {
+  return p.m * n * p.R_g * T / (0.5 * p.Kn * std::pow(T, p.omega));
+}
+
+void state_free(tk_state* st) {
+  tk_ctx* ctx = st->ctx;
+  for (void* p : st->allocs) ctx_free(ctx, p);
+  st->allocs.clear();
+}
+
+static void* st_alloc(tk_state* st, size_t bytes, tk_status* s) {
+  void* p = ctx_alloc(st->ctx, bytes, s);
+  if (p) st->allocs.push_back(p);
+  return p;
+}
+
+DevState state_dev(const tk_state* st) {
+  DevState d;
+  d.n_cells = st->nc;
+  d.N = st->N;
+  d.CS = st->CS;
+  d.inst = st->d_inst;
+  d.ip = st->d_ip;
+  d.slot_nb = st->d_slot_nb;
+  d.slot_kind = st->d_slot_kind;
+  d.slot_axis = st->d_slot_axis;
+  d.slot_sig = st->d_slot_sig;
+  d.slot_coef = st->d_slot_coef;
+  d.bc_fac = st->d_bc_fac;
+  d.core = st->core[st->cur];
+  d.fac = st->fac[st->cur];
+  d.rank = st->rank[st->cur];
+  d.core_n = st->core[st->cur ^ 1];
+  d.fac_n = st->fac[st->cur ^ 1];
+  d.rank_n = st->rank[st->cur ^ 1];
+  d.macro = st->d_macro;
+  d.nu = st->d_nu;
+  d.nw = st->d_nw;
+  d.flag = st->d_flag;
+  return d;
+}
+
+DevPlain plain_dev(const tk_state* st) {
+  DevPlain d;
+  d.n_cells = st->nc;
+  d.N = st->N;
+  d.inst = st->d_inst;
+  d.ip = st->d_ip;
+  d.slot_nb = st->d_slot_nb;
+  d.slot_kind = st->d_slot_kind;
+  d.slot_axis = st->d_slot_axis;
+  d.slot_sig = st->d_slot_sig;
+  d.slot_coef = st->d_slot_coef;
+  d.bc_fac = st->d_bc_fac;
+  d.f = st->pf[st->cur];
+  d.f_n = st->pf[st->cur ^ 1];
+  d.macro = st->d_macro;
+  d.nu = st->d_nu;
+  d.nw = st->d_nw;
+  d.flag = st->d_flag;
+  return d;
+}
+
+size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk) {
+  const size_t N = p.N, CS = std::max(4, p.rank_cap);
+  const size_t tsz = p.precision == TK_MIXED ? 4 : 8;
+  size_t b = (size_t)nc * (sizeof(int) + kSlots * (sizeof(int) + 3 + sizeof(double)) + 8 * 2 + 8 + 8 * kSlots + 8);
+  if (plain) {
+    b += 2 * (size_t)nc * N * N * N * tsz;
+  } else {
+    b += 2 * (size_t)nc * (CS * CS * CS + 3 * CS * N) * 8 + 2 * (size_t)nc * 3 * 4;
+    b += (size_t)chunk * (N * N * N * tsz + 3 * N * N * 8);
+  }
+  return b;
+}
+
+static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* meshes, const tk_params* params,
+                              const double* const* macros, bool plain, tk_state** out) {
+  if (!ctx || !out || count <= 0 || !meshes || !params || !macros) return ctx_fail(ctx, TK_EINVAL, "state: null argument");
+  *out = nullptr;
+  if (ctx->device < 0) return ctx_fail(ctx, TK_EDEVICE, "state: host-only context");
+  const int N = params[0].N;
+  const int prec = params[0].precision;
+  int CS = 4, nc = 0, nbc = 0;
+  for (int k = 0; k < count; ++k) {
+    tk_status s = check_params(ctx, &params[k]);
+    if (s != TK_OK) return s;
+    if (params[k].N != N || params[k].precision != prec)
+      return ctx_fail(ctx, TK_EINVAL, "state: all instances of a batch share N and precision");
+    if (!meshes[k] || !macros[k]) return ctx_fail(ctx, TK_EINVAL, "state: null mesh or macro");
+    CS = std::max(CS, params[k].rank_cap);
+    nc += meshes[k]->n_cells;
+    nbc += (int)meshes[k]->bc.size();
+  }
+  std::unique_ptr<tk_state> st(new tk_state());
+  st->ctx = ctx;
+  st->N = N;
+  st->CS = CS;
+  st->mixed = (prec == TK_MIXED);
+  st->plain = plain;
+  st->nc = nc;
+  st->ninst = count;
+  st->params.assign(params, params + count);
+  st->meshes.assign(meshes, meshes + count);
+  // host tables
+  std::vector<int> inst(nc), slot_nb((size_t)nc * kSlots);
+  std::vector<int8_t> slot_kind((size_t)nc * kSlots), slot_axis((size_t)nc * kSlots), slot_sig((size_t)nc * kSlots);
+  std::vector<double> slot_coef((size_t)nc * kSlots), vol(nc), bc_fac((size_t)std::max(nbc, 1) * 3 * N, 0.0);
+  std::vector<double> macro5((size_t)nc * 5);
+  std::vector<InstParams> ip(count);
+  st->inst_off.assign(count + 1, 0);
+  int c0 = 0, b0 = 0;
+  for (int k = 0; k < count; ++k) {
+    const tk_mesh* m = meshes[k];
+    const tk_params& p = params[k];
+    const double dxi = 2.0 * p.xi_max / (N - 1);
+    // time step of this instance
+    double dmax = 0.0;
+    for (int c = 0; c < m->n_cells; ++c) {
+      const double* mc = macros[k] + 5 * (size_t)c;
+      for (int a = 0; a < 5; ++a)
+        if (!std::isfinite(mc[a])) return ctx_fail(ctx, TK_ENUMERIC, "state: non-finite initial macroparameter");
+      if (!(mc[0] > 0.0) || !(mc[4] > 0.0)) return ctx_fail(ctx, TK_ENUMERIC, "state: initial n or T not positive");
+      double l1 = 0.0;
+      for (int s = 0; s < kSlots; ++s) l1 += m->slot_l1[(size_t)c * kSlots + s];
+      const double D = p.xi_max / (2.0 * m->volume[c]) * l1;
+      dmax = std::max(dmax, D + collision_freq(p, mc[0], mc[4]));
+    }
+    const double dt = p.cfl / dmax;
+    InstParams& P = ip[k];
+    P.xi_min = -p.xi_max;
+    P.dxi = dxi;
+    P.dt = dt;
+    P.Rg = p.R_g;
+    P.m = p.m;
+    P.Pr = p.Pr;
+    P.omega = p.omega;
+    P.Kn = p.Kn;
+    P.tol = p.tol;
+    P.cap = p.rank_cap;
+    P.pad = 0;
+    for (int c = 0; c < m->n_cells; ++c) {
+      const int g = c0 + c;
+      inst[g] = k;
+      vol[g] = m->volume[c];
+      std::memcpy(&macro5[5 * (size_t)g], macros[k] + 5 * (size_t)c, 5 * sizeof(double));
+      for (int s = 0; s < kSlots; ++s) {
+        const size_t src = (size_t)c * kSlots + s, dst = (size_t)g * kSlots + s;
+        const int8_t kind = m->slot_kind[src];
+        slot_kind[dst] = kind;
+        slot_axis[dst] = m->slot_axis[src];
+        slot_sig[dst] = m->slot_sig[src];
+        slot_coef[dst] = dt * m->slot_area[src] / m->volume[c];
+        slot_nb[dst] = (kind == SK_INTERIOR) ? m->slot_nb[src] + c0 : (kind == SK_NONE ? -1 : m->slot_nb[src] + b0);
+      }
+    }
+    // rank-1 boundary Maxwellian factors
+    for (size_t b = 0; b < m->bc.size(); ++b) {
+      const tk_bc& bc = m->bc[b];
+      double n = 0, T = 0, u[3] = {0, 0, 0};
+      if (bc.kind == TK_BC_INFLOW) {
+        n = bc.n; T = bc.T; u[0] = bc.u[0]; u[1] = bc.u[1]; u[2] = bc.u[2];
+        if (!(n > 0) || !(T > 0)) return ctx_fail(ctx, TK_EINVAL, "state: inflow n and T must be positive");
+      } else if (bc.kind == TK_BC_WALL) {
+        n = 1.0; T = bc.T_w;
+        if (!(T > 0)) return ctx_fail(ctx, TK_EINVAL, "state: wall temperature must be positive");
+      } else {
+        continue;
+      }
+      const double amp = std::cbrt(n) / std::sqrt(2.0 * M_PI * p.R_g * T);
+      for (int a = 0; a < 3; ++a)
+        for (int i = 0; i < N; ++i) {
+          const double x = -p.xi_max + i * dxi - u[a];
+          bc_fac[((size_t)(b0 + b) * 3 + a) * N + i] = amp * std::exp(-x * x / (2.0 * p.R_g * T));
+        }
+    }
+    st->inst_off[k] = c0;
+    c0 += m->n_cells;
+    b0 += (int)m->bc.size();
+  }
+  st->inst_off[count] = c0;
+  st->ip_host = ip;
+  // chunk of cells processed per rounding pass
+  const size_t tsz = st->mixed ? 4 : 8;
+  const size_t per = (size_t)N * N * N * tsz + 3 * (size_t)N * N * 8;
+  size_t ws = std::min<size_t>(ctx->budget / 4, (size_t)4 << 30);
+  st->chunk = (int)std::max<size_t>(1, std::min<size_t>(nc, ws / per));
+  // device allocations
+  tk_status s = TK_OK;
+  tk_state* S = st.get();
+#define ALLOC(ptr, type, n)                                                    \
+  do {                                                                         \
+    S->ptr = (type*)st_alloc(S, sizeof(type) * (size_t)(n), &s);               \
+    if (!S->ptr) { state_free(S); return s; }                                  \
+  } while (0)
+  ALLOC(d_inst, int, nc);
+  ALLOC(d_ip, InstParams, count);
+  ALLOC(d_slot_nb, int, (size_t)nc * kSlots);
+  ALLOC(d_slot_kind, int8_t, (size_t)nc * kSlots);
+  ALLOC(d_slot_axis, int8_t, (size_t)nc * kSlots);
+  ALLOC(d_slot_sig, int8_t, (size_t)nc * kSlots);
+  ALLOC(d_slot_coef, double, (size_t)nc * kSlots);
+  ALLOC(d_bc_fac, double, (size_t)std::max(nbc, 1) * 3 * N);
+  ALLOC(d_vol, double, nc);
+  ALLOC(d_inst_off, int, count + 1);
+  ALLOC(d_macro, double, (size_t)nc * 8);
+  ALLOC(d_macro_prev, double, (size_t)nc * 8);
+  ALLOC(d_nu, double, nc);
+  ALLOC(d_nw, double, (size_t)nc * kSlots);
+  ALLOC(d_flag, int, 1);
+  ALLOC(d_resid, double, count);
+  ALLOC(d_macro5, double, (size_t)nc * 5);
+  if (plain) {
+    for (int b = 0; b < 2; ++b) {
+      S->pf[b] = st_alloc(S, tsz * (size_t)nc * N * N * N, &s);
+      if (!S->pf[b]) { state_free(S); return s; }
+    }
+  } else {
+    for (int b = 0; b < 2; ++b) {
+      ALLOC(core[b], double, (size_t)nc * CS * CS * CS);
+      ALLOC(fac[b], double, (size_t)nc * 3 * CS * N);
+      ALLOC(rank[b], int, (size_t)nc * 3);
+    }
+    S->X = st_alloc(S, per * 0 + (size_t)S->chunk * N * N * N * tsz, &s);
+    if (!S->X) { state_free(S); return s; }
+    ALLOC(G, double, (size_t)S->chunk * 3 * N * N);
+    if (!S->mixed) ALLOC(Wb, double, (size_t)S->chunk * 3 * N * N);
+  }
+#undef ALLOC
+  hipStream_t q = ctx->stream;
+  hipError_t e = hipSuccess;
+  auto up = [&](void* dst, const void* src, size_t n) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, q);
+  };
+  up(S->d_inst, inst.data(), sizeof(int) * nc);
+  up(S->d_ip, ip.data(), sizeof(InstParams) * count);
+  up(S->d_slot_nb, slot_nb.data(), sizeof(int) * slot_nb.size());
+  up(S->d_slot_kind, slot_kind.data(), slot_kind.size());
+  up(S->d_slot_axis, slot_axis.data(), slot_axis.size());
+  up(S->d_slot_sig, slot_sig.data(), slot_sig.size());
+  up(S->d_slot_coef, slot_coef.data(), sizeof(double) * slot_coef.size());
+  up(S->d_bc_fac, bc_fac.data(), sizeof(double) * bc_fac.size());
+  up(S->d_vol, vol.data(), sizeof(double) * nc);
+  up(S->d_inst_off, st->inst_off.data(), sizeof(int) * (count + 1));
+  up(S->d_macro5, macro5.data(), sizeof(double) * macro5.size());
+  if (e == hipSuccess) e = hipMemsetAsync(S->d_flag, 0, sizeof(int), q);
+  if (e == hipSuccess) e = hipMemsetAsync(S->d_nw, 0, sizeof(double) * (size_t)nc * kSlots, q);
+  if (e == hipSuccess) e = hipMemsetAsync(S->d_macro, 0, sizeof(double) * (size_t)nc * 8, q);
+  if (e != hipSuccess) { state_free(S); return ctx_hip(ctx, e, "state upload"); }
+  S->cur = 0;
+  if (plain) {
+    e = launch_plain_init(plain_dev(S), S->d_macro5, S->mixed, q);
+  } else {
+    // zero both buffers' padding, then the rank-1 Maxwellians
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+      e = hipMemsetAsync(S->core[b], 0, sizeof(double) * (size_t)nc * CS * CS * CS, q);
+      if (e == hipSuccess) e = hipMemsetAsync(S->fac[b], 0, sizeof(double) * (size_t)nc * 3 * CS * N, q);
+      if (e == hipSuccess) e = hipMemsetAsync(S->rank[b], 0, sizeof(int) * (size_t)nc * 3, q);
+    }
+    if (e == hipSuccess) e = launch_init_maxwell(state_dev(S), S->d_macro5, q);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(q);
+  if (e != hipSuccess) { state_free(S); return ctx_hip(ctx, e, "state init"); }
+  *out = st.release();
+  return TK_OK;
+}
+
+// one explicit step of every instance of the state
+static tk_status state_step_once(tk_state* st) {
+  tk_ctx* ctx = st->ctx;
+  hipStream_t q = ctx->stream;
+  hipError_t e;
+  hipEvent_t ev;
+  if (st->plain) {
+    DevPlain d = plain_dev(st);
+    prof_begin(ctx, KID_PLAIN_MOM, &ev);
+    e = launch_plain_moments(d, st->mixed, q);
+    prof_end(ctx, KID_PLAIN_MOM, ev);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "plain moments");
+    prof_begin(ctx, KID_PLAIN_STEP, &ev);
+    e = launch_plain_step(d, st->mixed, q);
+    prof_end(ctx, KID_PLAIN_STEP, ev);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "plain step");
+    st->cur ^= 1;
+    return TK_OK;
+  }
+  DevState d = state_dev(st);
+  prof_begin(ctx, KID_MOMENTS, &ev);
+  e = launch_moments(d, q);
+  prof_end(ctx, KID_MOMENTS, ev);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "moments");
+  for (int c0 = 0; c0 < st->nc; c0 += st->chunk) {
+    const int cnt = std::min(st->chunk, st->nc - c0);
+    prof_begin(ctx, KID_EXPAND, &ev);
+    e = launch_expand(d, c0, cnt, st->X, st->mixed, q);
+    prof_end(ctx, KID_EXPAND, ev);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "expand");
+    prof_begin(ctx, KID_GRAM, &ev);
+    e = launch_gram(st->N, cnt, st->X, st->mixed, st->G, q);
+    prof_end(ctx, KID_GRAM, ev);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "gram");
+    prof_begin(ctx, KID_EIG, &ev);
+    if (st->mixed) {
+      e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
+                     nullptr, q);
+    } else {
+      // FP64 path: first basis, Gram of the rotated unfoldings, final basis
+      e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
+                     st->Wb, q);
+      if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, st->X, 0, st->Wb, st->G, q);
+      if (e == hipSuccess)
+        e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, st->Wb,
+                       nullptr, q);
+    }
+    prof_end(ctx, KID_EIG, ev);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "eig");
+    prof_begin(ctx, KID_PROJECT, &ev);
+    e = launch_project(st->N, cnt, st->X, st->mixed, c0, st->CS, d.fac_n, d.rank_n, d.core_n, q);
+    prof_end(ctx, KID_PROJECT, ev);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "project");
+  }
+  st->cur ^= 1;
+  return TK_OK;
+}
+
+tk_status state_moments_now(tk_state* st) {
+  hipError_t e;
+  if (st->plain) e = launch_plain_moments(plain_dev(st), st->mixed, st->ctx->stream);
+  else e = launch_moments(state_dev(st), st->ctx->stream);
+  return ctx_hip(st->ctx, e, "moments");
+}
+
+tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait) {
+  tk_ctx* ctx = st->ctx;
+  hipStream_t q = ctx->stream;
+  tk_status s;
+  for (int k = 0; k < nsteps; ++k) {
+    if (residual && k == nsteps - 1) {
+      if ((s = state_moments_now(st)) != TK_OK) return s;
+      hipError_t e = hipMemcpyAsync(st->d_macro_prev, st->d_macro, sizeof(double) * (size_t)st->nc * 8,
+                                    hipMemcpyDeviceToDevice, q);
+      if (e != hipSuccess) return ctx_hip(ctx, e, "macro copy");
+    }
+    if ((s = state_step_once(st)) != TK_OK) return s;
+  }
+  if (!wait) return TK_OK;
+  if ((s = state_moments_now(st)) != TK_OK) return s;
+  if (residual && nsteps > 0) {
+    hipError_t e = launch_residual(st->d_macro_prev, st->d_macro, st->d_vol, st->d_inst_off, st->ninst, st->d_resid, q);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(residual, st->d_resid, sizeof(double) * st->ninst, hipMemcpyDeviceToHost, q);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "residual");
+  }
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, st->d_flag, sizeof(int), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipStreamSynchronize(q);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "step sync");
+  prof_harvest(ctx);
+  if (flag) return ctx_fail(ctx, TK_ENUMERIC, "a cell has non-positive or non-finite n or T");
+  return TK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+tk_status tk_ctx_create(int32_t device, size_t hbm_budget, void* hip_stream, tk_ctx** out) {
+  if (!out) return TK_EINVAL;
+  *out = nullptr;
+  if (device == -1) {
+    // host-only context: mesh loading and validation, no device work
+    std::unique_ptr<tk_ctx> c(new tk_ctx());
+    c->device = -1;
+    *out = c.release();
+    return TK_OK;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TK_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return TK_EDEVICE;
+  std::unique_ptr<tk_ctx> c(new tk_ctx());
+  c->device = device;
+  size_t freeb = 0, total = 0;
+  if (hipMemGetInfo(&freeb, &total) != hipSuccess) return TK_EDEVICE;
+  c->budget = hbm_budget ? hbm_budget : (size_t)(0.9 * (double)freeb);
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+    c->own_stream = false;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return TK_EDEVICE;
+    c->own_stream = true;
+  }
+  *out = c.release();
+  return TK_OK;
+}
+
+tk_status tk_ctx_destroy(tk_ctx* ctx) {
+  if (!ctx) return TK_EINVAL;
+  if (ctx->device < 0) {
+    delete ctx;
+    return TK_OK;
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (auto& p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return TK_OK;
+}
+
+const char* tk_last_error(const tk_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+tk_status tk_sync(tk_ctx* ctx) {
+  if (!ctx) return TK_EINVAL;
+  if (ctx->device < 0) return TK_OK;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  tk_status s = ctx_hip(ctx, hipStreamSynchronize(ctx->stream), "sync");
+  prof_harvest(ctx);
+  return s;
+}
+
+tk_status tk_prof_enable(tk_ctx* ctx, int32_t on) {
+  if (!ctx) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  ctx->prof = on != 0;
+  return TK_OK;
+}
+
+tk_status tk_prof_get(tk_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches) {
+  if (!ctx || !kernel) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  prof_harvest(ctx);
+  for (int k = 0; k < KID_COUNT; ++k)
+    if (std::strcmp(kernel, kKernelNames[k]) == 0) {
+      if (total_ms) *total_ms = ctx->prof_ms[k];
+      if (launches) *launches = ctx->prof_n[k];
+      return TK_OK;
+    }
+  return ctx_fail(ctx, TK_ENOTFOUND, std::string("unknown kernel family ") + kernel);
+}
+
+tk_status tk_prof_reset(tk_ctx* ctx) {
+  if (!ctx) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  prof_harvest(ctx);
+  for (int k = 0; k < KID_COUNT; ++k) { ctx->prof_ms[k] = 0.0; ctx->prof_n[k] = 0; }
+  return TK_OK;
+}
+
+tk_status tk_mesh_load(tk_ctx* ctx, const tk_mesh_desc* desc, tk_mesh** out) {
+  if (!ctx || !out) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  *out = nullptr;
+  std::unique_ptr<tk_mesh> m(new tk_mesh());
+  m->ctx = ctx;
+  tk_status s = mesh_build(ctx, desc, m.get());
+  if (s != TK_OK) return s;
+  *out = m.release();
+  return TK_OK;
+}
+
+tk_status tk_mesh_destroy(tk_mesh* mesh) {
+  if (!mesh) return TK_EINVAL;
+  delete mesh;
+  return TK_OK;
+}
+
+tk_status tk_state_init(tk_ctx* ctx, const tk_mesh* mesh, const tk_params* params, const double* macro,
+                        tk_state** out) {
+  if (!ctx) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  return state_create(ctx, 1, &mesh, params, &macro, false, out);
+}
+
+tk_status tk_state_init_batch(tk_ctx* ctx, int32_t count, const tk_mesh* const* meshes, const tk_params* params,
+                              const double* const* macros, tk_state** out) {
+  if (!ctx) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  return state_create(ctx, count, meshes, params, macros, false, out);
+}
+
+tk_status tk_plain_init(tk_ctx* ctx, const tk_mesh* mesh, const tk_params* params, const double* macro,
+                        tk_state** out) {
+  if (!ctx) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  return state_create(ctx, 1, &mesh, params, &macro, true, out);
+}
+
+tk_status tk_state_destroy(tk_state* st) {
+  if (!st) return TK_EINVAL;
+  tk_ctx* ctx = st->ctx;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  (void)hipStreamSynchronize(ctx->stream);
+  state_free(st);
+  delete st;
+  return TK_OK;
+}
+
+tk_status tk_state_info(const tk_state* st, int32_t* n_cells, int32_t* n_instances) {
+  if (!st) return TK_EINVAL;
+  if (n_cells) *n_cells = st->nc;
+  if (n_instances) *n_instances = st->ninst;
+  return TK_OK;
+}
+
+tk_status tk_state_dt(const tk_state* st, int32_t inst, double* dt) {
+  if (!st || !dt || inst < 0 || inst >= st->ninst) return TK_EINVAL;
+  *dt = st->ip_host[inst].dt;
+  return TK_OK;
+}
+
+tk_status tk_moments(tk_state* st, double* out) {
+  if (!st || !out) return TK_EINVAL;
+  tk_ctx* ctx = st->ctx;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  tk_status s = state_moments_now(st);
+  if (s != TK_OK) return s;
+  hipError_t e = hipMemcpyAsync(out, st->d_macro, sizeof(double) * (size_t)st->nc * 8, hipMemcpyDeviceToHost,
+                                ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  return ctx_hip(ctx, e, "moments copy");
+}
+
+tk_status tk_step(tk_state* st, int32_t nsteps, double* residual) {
+  if (!st || nsteps < 0) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(st->ctx->mu);
+  return state_steps(st, nsteps, residual, true);
+}
+
+tk_status tk_step_async(tk_state* st, int32_t nsteps) {
+  if (!st || nsteps < 0) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(st->ctx->mu);
+  return state_steps(st, nsteps, nullptr, false);
+}
+
+tk_status tk_state_ranks(tk_state* st, int32_t* ranks, double* mean_compression) {
+  if (!st) return TK_EINVAL;
+  tk_ctx* ctx = st->ctx;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  if (st->plain) return ctx_fail(ctx, TK_EINVAL, "plain state has no ranks");
+  std::vector<int> r((size_t)st->nc * 3);
+  hipError_t e = hipMemcpyAsync(r.data(), st->rank[st->cur], sizeof(int) * r.size(), hipMemcpyDeviceToHost,
+                                ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "ranks copy");
+  if (ranks) std::memcpy(ranks, r.data(), sizeof(int) * r.size());
+  if (mean_compression) {
+    const double N = st->N;
+    double acc = 0.0;
+    for (int c = 0; c < st->nc; ++c) {
+      const double r1 = r[3 * c], r2 = r[3 * c + 1], r3 = r[3 * c + 2];
+      acc += (r1 * r2 * r3 + N * (r1 + r2 + r3)) / (N * N * N);
+    }
+    *mean_compression = acc / st->nc;
+  }
+  return TK_OK;
+}
+
+tk_status tk_state_export(tk_state* st, int32_t cell, tk_tucker* out) {
+  if (!st || !out || cell < 0 || cell >= st->nc || !out->core) return TK_EINVAL;
+  tk_ctx* ctx = st->ctx;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  if (st->plain) return ctx_fail(ctx, TK_EINVAL, "plain state has no Tucker form");
+  const int N = st->N, CS = st->CS;
+  std::vector<double> core((size_t)CS * CS * CS), fac((size_t)3 * CS * N);
+  int r[3];
+  hipStream_t q = ctx->stream;
+  hipError_t e = hipMemcpyAsync(r, st->rank[st->cur] + 3 * (size_t)cell, sizeof(r), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(core.data(), st->core[st->cur] + (size_t)cell * CS * CS * CS, sizeof(double) * core.size(),
+                       hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(fac.data(), st->fac[st->cur] + (size_t)cell * 3 * CS * N, sizeof(double) * fac.size(),
+                       hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipStreamSynchronize(q);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "export copy");
+  out->N = N;
+  for (int a = 0; a < 3; ++a) out->r[a] = r[a];
+  for (int k3 = 0; k3 < r[2]; ++k3)
+    for (int k2 = 0; k2 < r[1]; ++k2)
+      for (int k1 = 0; k1 < r[0]; ++k1)
+        out->core[k1 + r[0] * (k2 + r[1] * k3)] = core[k1 + CS * (k2 + CS * k3)];
+  for (int a = 0; a < 3; ++a) {
+    if (!out->U[a]) return ctx_fail(ctx, TK_EINVAL, "export: null factor buffer");
+    for (int k = 0; k < r[a]; ++k)
+      for (int i = 0; i < N; ++i) out->U[a][i + N * k] = fac[((size_t)a * CS + k) * N + i];
+  }
+  return TK_OK;
+}
+
+tk_status tk_round_tucker(tk_ctx* ctx, int32_t count, const tk_tucker* in, double tol, int32_t cap,
+                          tk_tucker* out) {
+  if (!ctx || count < 0 || (count > 0 && (!in || !out))) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  if (count == 0) return TK_OK;
+  if (ctx->device < 0) return ctx_fail(ctx, TK_EDEVICE, "round: host-only context");
+  const int N = in[0].N;
+  bool okN = false;
+  for (int n : kSupportedN) okN |= (N == n && n <= 32);
+  if (!okN) return ctx_fail(ctx, TK_EINVAL, "round: N must be 16, 24 or 32");
+  if (cap < 1 || cap > kMaxCap || cap > N || !(tol >= 0)) return ctx_fail(ctx, TK_EINVAL, "round: bad tol or cap");
+  int CSi = 1;
+  for (int k = 0; k < count; ++k) {
+    if (in[k].N != N) return ctx_fail(ctx, TK_EINVAL, "round: all tensors share N");
+    for (int a = 0; a < 3; ++a) {
+      if (in[k].r[a] < 1 || in[k].r[a] > N) return ctx_fail(ctx, TK_EINVAL, "round: a rank exceeds N");
+      if (in[k].r[a] > kMaxCap) return ctx_fail(ctx, TK_EINVAL, "round: input ranks above 16 are not supported");
+      CSi = std::max(CSi, in[k].r[a]);
+    }
+  }
+  const int CSo = cap;
+  std::vector<double> core((size_t)count * CSi * CSi * CSi, 0.0), fac((size_t)count * 3 * CSi * N, 0.0);
+  std::vector<int> rk((size_t)count * 3);
+  for (int k = 0; k < count; ++k) {
+    const tk_tucker& t = in[k];
+    for (int a = 0; a < 3; ++a) rk[3 * k + a] = t.r[a];
+    for (int k3 = 0; k3 < t.r[2]; ++k3)
+      for (int k2 = 0; k2 < t.r[1]; ++k2)
+        for (int k1 = 0; k1 < t.r[0]; ++k1)
+          core[(size_t)k * CSi * CSi * CSi + k1 + CSi * (k2 + CSi * k3)] = t.core[k1 + t.r[0] * (k2 + t.r[1] * k3)];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < t.r[a]; ++c)
+        for (int i = 0; i < N; ++i) fac[(((size_t)k * 3 + a) * CSi + c) * N + i] = t.U[a][i + N * c];
+  }
+  tk_status s = TK_OK;
+  std::vector<void*> mem;
+  auto A = [&](size_t b) -> void* {
+    void* p = ctx_alloc(ctx, b, &s);
+    if (p) mem.push_back(p);
+    return p;
+  };
+  double* d_core = (double*)A(sizeof(double) * core.size());
+  double* d_fac = d_core ? (double*)A(sizeof(double) * fac.size()) : nullptr;
+  int* d_rk = d_fac ? (int*)A(sizeof(int) * rk.size()) : nullptr;
+  double* d_X = d_rk ? (double*)A(sizeof(double) * (size_t)count * N * N * N) : nullptr;
+  double* d_G = d_X ? (double*)A(sizeof(double) * (size_t)count * 3 * N * N) : nullptr;
+  double* d_fo = d_G ? (double*)A(sizeof(double) * (size_t)count * 3 * CSo * N) : nullptr;
+  int* d_ro = d_fo ? (int*)A(sizeof(int) * (size_t)count * 3) : nullptr;
+  double* d_co = d_ro ? (double*)A(sizeof(double) * (size_t)count * CSo * CSo * CSo) : nullptr;
+  double* d_W = d_co ? (double*)A(sizeof(double) * (size_t)count * 3 * N * N) : nullptr;
+  auto cleanup = [&]() { for (void* p : mem) ctx_free(ctx, p); };
+  if (!d_W) { cleanup(); return s; }
+  hipStream_t q = ctx->stream;
+  hipError_t e = hipMemcpyAsync(d_core, core.data(), sizeof(double) * core.size(), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_fac, fac.data(), sizeof(double) * fac.size(), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_rk, rk.data(), sizeof(int) * rk.size(), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess) e = launch_expand_plain(N, count, CSi, d_core, d_fac, d_rk, d_X, q);
+  if (e == hipSuccess) e = launch_gram(N, count, d_X, 0, d_G, q);
+  if (e == hipSuccess) e = launch_eig(N, count, d_G, nullptr, nullptr, 0, tol, cap, CSo, d_fo, d_ro, nullptr, d_W, q);
+  if (e == hipSuccess) e = launch_gram_rot(N, count, d_X, 0, d_W, d_G, q);
+  if (e == hipSuccess) e = launch_eig(N, count, d_G, nullptr, nullptr, 0, tol, cap, CSo, d_fo, d_ro, d_W, nullptr, q);
+  if (e == hipSuccess) e = launch_project(N, count, d_X, 0, 0, CSo, d_fo, d_ro, d_co, q);
+  std::vector<double> co((size_t)count * CSo * CSo * CSo), fo((size_t)count * 3 * CSo * N);
+  std::vector<int> ro((size_t)count * 3);
+  if (e == hipSuccess) e = hipMemcpyAsync(co.data(), d_co, sizeof(double) * co.size(), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(fo.data(), d_fo, sizeof(double) * fo.size(), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(ro.data(), d_ro, sizeof(int) * ro.size(), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipStreamSynchronize(q);
+  cleanup();
+  if (e != hipSuccess) return ctx_hip(ctx, e, "round");
+  for (int k = 0; k < count; ++k) {
+    tk_tucker& t = out[k];
+    if (!t.core || !t.U[0] || !t.U[1] || !t.U[2]) return ctx_fail(ctx, TK_EINVAL, "round: null output buffer");
+    t.N = N;
+    for (int a = 0; a < 3; ++a) t.r[a] = ro[3 * k + a];
+    for (int k3 = 0; k3 < t.r[2]; ++k3)
+      for (int k2 = 0; k2 < t.r[1]; ++k2)
+        for (int k1 = 0; k1 < t.r[0]; ++k1)
+          t.core[k1 + t.r[0] * (k2 + t.r[1] * k3)] = co[(size_t)k * CSo * CSo * CSo + k1 + CSo * (k2 + CSo * k3)];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < t.r[a]; ++c)
+        for (int i = 0; i < N; ++i) t.U[a][i + N * c] = fo[(((size_t)k * 3 + a) * CSo + c) * N + i];
+  }
+  return TK_OK;
+}
+
+}  // extern "C"

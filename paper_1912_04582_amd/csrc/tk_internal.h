@@ -1,0 +1,117 @@
+// Internal declarations of the tk library (device layouts, kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "tk.h"
+
+namespace tk {
+
+constexpr int kMaxCap = 16;  // largest Tucker rank per mode
+constexpr int kSlots = 6;    // faces per hexahedral cell
+
+// Kind of the cell on the far side of a face slot.
+enum SlotKind : int8_t {
+  SK_NONE = -1,     // unused slot (cell with fewer than 6 faces)
+  SK_INTERIOR = 0,  // another cell of the same state
+  SK_INFLOW = 1,    // free-stream Maxwellian
+  SK_OUTFLOW = 2,   // zero-gradient: the cell itself
+  SK_SYM = 3,       // symmetry plane: the cell with one velocity axis reversed
+  SK_WALL = 4,      // diffuse wall: n_w times the unit wall Maxwellian
+};
+
+// Per-instance parameters, device resident (one entry per instance).
+struct InstParams {
+  double xi_min, dxi;
+  double dt, Rg, m, Pr, omega, Kn, tol;
+  int cap;
+  int pad;
+};
+
+// Device views used by the step kernels.  Factor storage: fac[cell][a][k][i]
+// (column k of mode a, N contiguous); core storage: core[cell][k1 + CS (k2 +
+// CS k3)] with CS the state's storage cap; ranks rank[cell][3].
+struct DevState {
+  int n_cells;
+  int N;
+  int CS;                  // storage cap (max over instances)
+  const int* inst;         // [nc]
+  const InstParams* ip;    // [n_inst]
+  const int* slot_nb;      // [nc][6] neighbour cell, or global bc index
+  const int8_t* slot_kind; // [nc][6]
+  const int8_t* slot_axis; // [nc][6]
+  const int8_t* slot_sig;  // [nc][6] outward orientation along the axis
+  const double* slot_coef; // [nc][6] dt * A / V
+  const double* bc_fac;    // [n_bc][3][N] rank-1 boundary Maxwellian factors
+  // state, current buffer
+  const double* core;
+  const double* fac;
+  const int* rank;
+  // state, next buffer
+  double* core_n;
+  double* fac_n;
+  int* rank_n;
+  // per-cell macro (n,u1,u2,u3,T,q1,q2,q3), collision frequency, wall ghosts
+  double* macro;
+  double* nu;
+  double* nw;      // [nc][6]
+  int* flag;       // numeric error flag
+};
+
+// Kernel families (names used by the profiler interface).
+enum KernelId { KID_MOMENTS = 0, KID_EXPAND, KID_GRAM, KID_EIG, KID_PROJECT, KID_INIT, KID_PLAIN_MOM,
+                KID_PLAIN_STEP, KID_RESID, KID_COUNT };
+extern const char* kKernelNames[KID_COUNT];
+
+// ---- launchers (each enqueues on `s`) -------------------------------------
+hipError_t launch_init_maxwell(const DevState& d, const double* macro5, hipStream_t s);
+hipError_t launch_moments(const DevState& d, hipStream_t s);
+hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixed, hipStream_t s);
+hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hipStream_t s);
+// eig of Grams [count][3][N][N]; writes factors/ranks of cells c0.. into the
+// next buffers (tol/cap per instance via inst/ip, or the overrides when
+// inst == nullptr)
+hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
+                      double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
+                      const double* Win, double* Wout, hipStream_t s);
+// Gram of the rotated unfoldings: G2_a = (W_a^T A_(a)) (W_a^T A_(a))^T
+hipError_t launch_gram_rot(int N, int count, const void* X, int mixed, const double* W, double* G2,
+                           hipStream_t s);
+hipError_t launch_project(int N, int count, const void* X, int mixed, int c0, int CS, const double* fac_n,
+                          const int* rank_n, double* core_n, hipStream_t s);
+// generic expansion of `count` Tucker tensors given in the state layout into X (fp64)
+hipError_t launch_expand_plain(int N, int count, int CS, const double* core, const double* fac,
+                               const int* rank, double* X, hipStream_t s);
+hipError_t launch_residual(const double* macro_old, const double* macro_new, const double* vol,
+                           const int* inst_off, int n_inst, double* out, hipStream_t s);
+
+// plain full-tensor comparator
+struct DevPlain {
+  int n_cells;
+  int N;
+  const int* inst;
+  const InstParams* ip;
+  const int* slot_nb;
+  const int8_t* slot_kind;
+  const int8_t* slot_axis;
+  const int8_t* slot_sig;
+  const double* slot_coef;
+  const double* bc_fac;
+  const void* f;   // [nc][N^3] float or double
+  void* f_n;
+  double* macro;
+  double* nu;
+  double* nw;
+  int* flag;
+};
+hipError_t launch_plain_init(const DevPlain& d, const double* macro5, int mixed, hipStream_t s);
+hipError_t launch_plain_moments(const DevPlain& d, int mixed, hipStream_t s);
+hipError_t launch_plain_step(const DevPlain& d, int mixed, hipStream_t s);
+
+}  // namespace tk

@@ -1,0 +1,92 @@
+// Host-side objects behind the opaque handles of tk.h.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "tk_internal.h"
+
+struct tk_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0;
+  size_t used = 0;
+  std::map<void*, size_t> sizes;
+  std::string err;
+  std::recursive_mutex mu;
+  // per-kernel-family timing
+  bool prof = false;
+  struct Pending {
+    int kid;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[tk::KID_COUNT] = {};
+  int64_t prof_n[tk::KID_COUNT] = {};
+};
+
+struct tk_mesh {
+  tk_ctx* ctx = nullptr;
+  int n_cells = 0, n_faces = 0;
+  std::vector<double> volume;
+  std::vector<tk_bc> bc;
+  // per cell, kSlots face slots
+  std::vector<int> slot_nb;        // neighbour cell or local bc index
+  std::vector<int8_t> slot_kind;   // tk::SlotKind
+  std::vector<int8_t> slot_axis;
+  std::vector<int8_t> slot_sig;    // outward orientation along the axis
+  std::vector<double> slot_area;
+  std::vector<double> slot_l1;     // A ||e||_1
+};
+
+struct tk_state {
+  tk_ctx* ctx = nullptr;
+  int N = 0, CS = 0;
+  bool mixed = false, plain = false;
+  int nc = 0, ninst = 0;
+  int chunk = 1;
+  std::vector<tk_params> params;
+  std::vector<const tk_mesh*> meshes;
+  std::vector<int> inst_off;
+  std::vector<tk::InstParams> ip_host;
+  std::vector<void*> allocs;
+  // device tables
+  int* d_inst = nullptr;
+  tk::InstParams* d_ip = nullptr;
+  int* d_slot_nb = nullptr;
+  int8_t* d_slot_kind = nullptr;
+  int8_t* d_slot_axis = nullptr;
+  int8_t* d_slot_sig = nullptr;
+  double* d_slot_coef = nullptr;
+  double* d_bc_fac = nullptr;
+  double* d_vol = nullptr;
+  int* d_inst_off = nullptr;
+  double* d_macro = nullptr;
+  double* d_macro_prev = nullptr;
+  double* d_macro5 = nullptr;
+  double* d_nu = nullptr;
+  double* d_nw = nullptr;
+  int* d_flag = nullptr;
+  double* d_resid = nullptr;
+  // Tucker state, double buffered
+  double* core[2] = {nullptr, nullptr};
+  double* fac[2] = {nullptr, nullptr};
+  int* rank[2] = {nullptr, nullptr};
+  int cur = 0;
+  // rounding workspaces
+  void* X = nullptr;
+  double* G = nullptr;
+  double* Wb = nullptr;  // first-pass bases of the FP64 refinement
+  // plain comparator storage
+  void* pf[2] = {nullptr, nullptr};
+};
+
+// shared helpers (runtime.hip)
+tk_status ctx_fail(tk_ctx* ctx, tk_status st, const std::string& msg);
+tk_status ctx_hip(tk_ctx* ctx, hipError_t e, const char* what);
+void* ctx_alloc(tk_ctx* ctx, size_t bytes, tk_status* st);
+void ctx_free(tk_ctx* ctx, void* p);
+tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait);
+size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk);

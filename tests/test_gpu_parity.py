@@ -1,0 +1,186 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: the FP64 path matches the oracle to 1e-10 relative on n, u, T
+and q (u against the thermal speed, q against p sqrt(2 R_g T)); the mixed
+path (FP32 term assembly, FP64 Gram/eigen/projection/moments) to 1e-5.
+Rank decisions must agree; where they cannot (a tail sum within rounding
+of the threshold) the oracle's decision margin is reported.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import macro_rel_err, tucker_full
+from oracle import dvm, fv, kinetic as kin, tucker as otk, tucker_dvm as td
+from paper_1912_04582_amd import tk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tk.Context(0)
+    yield c
+    c.close()
+
+
+def small_channel(N=16, cap=6, tol=1e-6, precision="fp64", Kn=0.1, nx=6):
+    m = synth.channel_with_obstacle(nx=nx, ny=4, nz=4, h=0.25, obstacle=((2, 3), (1, 2), (1, 3)),
+                                    inflow=(1.0, (0.8, 0.0, 0.0), 1.0), Tw=1.3)
+    cfg = dict(N=N, xi_max=4.5, cap=cap, tol=tol, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=Kn, Rg=0.5, m=1.0,
+               seed=11, init="random", precision=precision)
+    return m, cfg
+
+
+def oracle_macros(S, states):
+    return np.array([td.macros_of(S, states[i]) for i in range(S.mesh["n_cells"])])
+
+
+def gpu_state(ctx, m, cfg, macros):
+    mesh = tk.Mesh(ctx, m)
+    st = tk.State(ctx, mesh, cfg, macros)
+    return mesh, st
+
+
+@pytest.mark.parametrize("N", [16, 24, 32])
+def test_round_tucker_matches_oracle_hosvd(ctx, N):
+    rng = np.random.default_rng(N)
+    x = np.linspace(-3, 3, N)
+    tensors, refs = [], []
+    for t in range(6):
+        # smooth low-rank part plus a decaying random part: ranks above and
+        # below the cap, tails above and below the threshold
+        terms = [otk.hosvd(np.exp(-(x[:, None, None] - c) ** 2 - (x[None, :, None] + c) ** 2 / (1 + c)
+                                  - x[None, None, :] ** 2 * (1 + 0.5 * c)), 0.0, 4) for c in (0.2, 0.7)]
+        r = (3 + t, 5, 2 + t)
+        G = rng.standard_normal(r) * (10.0 ** -np.arange(r[0]))[:, None, None]
+        U = [np.linalg.qr(rng.standard_normal((N, r[a])))[0] for a in range(3)]
+        terms.append(otk.Tucker(1e-3 * G, U))
+        s = terms[0]
+        for q in terms[1:]:
+            s = otk.add(s, q)
+        tensors.append((s.G, s.U))
+        refs.append(otk.full(s))
+    for tol, cap in ((1e-6, 12), (1e-3, 16), (1e-9, 5)):
+        out = ctx.round_tucker(tensors, tol, cap)
+        for (G, U), A in zip(out, refs):
+            ref = otk.hosvd(A, tol, cap)
+            assert tuple(G.shape) == ref.ranks, (G.shape, ref.ranks)
+            B = tucker_full(G, U)
+            err = np.abs(B - otk.full(ref)).max() / np.abs(A).max()
+            assert err < 1e-11, err
+            for a in range(3):
+                np.testing.assert_allclose(U[a].T @ U[a], np.eye(U[a].shape[1]), atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["cfg0"])
+def test_initial_moments(ctx, name):
+    cfg = synth.make_config(name)
+    m = synth.configs.make_mesh(cfg)
+    m0 = synth.initial_macros(cfg, m)
+    mesh, st = gpu_state(ctx, m, cfg, m0)
+    got = st.moments()
+    S = fv.Setup(m, cfg, m0)
+    ref = oracle_macros(S, td.initial_states(S, m0))
+    err, _ = macro_rel_err(got, ref)
+    assert err < 1e-13, err
+    assert abs(st.dt() - S.dt) <= 1e-15 * S.dt
+    st.close(); mesh.close()
+
+
+def compare_states(st, S, ref_states, N, cells, tol_rel):
+    worst = 0.0
+    for i in cells:
+        G, U = st.export(i, N)
+        ref = ref_states[i]
+        assert tuple(G.shape) == ref.ranks, (i, G.shape, ref.ranks)
+        A = otk.full(ref)
+        err = np.abs(tucker_full(G, U) - A).max() / np.abs(A).max()
+        worst = max(worst, err)
+    assert worst < tol_rel, worst
+    return worst
+
+
+def test_cfg0_one_step_per_cell(ctx):
+    cfg = synth.make_config("cfg0")
+    m = synth.configs.make_mesh(cfg)
+    m0 = synth.initial_macros(cfg, m)
+    mesh, st = gpu_state(ctx, m, cfg, m0)
+    S = fv.Setup(m, cfg, m0)
+    st.step(1)
+    cells = [0, 1, 63, 200, 511]
+    ref = td.step(S, td.initial_states(S, m0), cells)
+    # one-step states from the plain definition as well
+    ref1 = dvm.step_full(S, dvm.initial_full(S, m0), cells)
+    compare_states(st, S, ref, 16, cells, 1e-11)
+    compare_states(st, S, ref1, 16, cells, 1e-11)
+    st.close(); mesh.close()
+
+
+def test_cfg0_full_run_fp64(ctx):
+    """The small workload end to end: 512 cells, N = 16, cap 6, 20 steps."""
+    cfg = synth.make_config("cfg0")
+    m = synth.configs.make_mesh(cfg)
+    m0 = synth.initial_macros(cfg, m)
+    mesh, st = gpu_state(ctx, m, cfg, m0)
+    st.step(cfg["steps"])
+    got = st.moments()
+    S = fv.Setup(m, cfg, m0)
+    ref_states = td.run(S, m0, cfg["steps"])
+    ref = oracle_macros(S, ref_states)
+    err, _ = macro_rel_err(got, ref)
+    print(f"cfg0 20 steps FP64 max rel macro err {err:.3e}")
+    assert err < 1e-10, err
+    ranks, C = st.ranks()
+    oranks = np.array([ref_states[i].ranks for i in range(m["n_cells"])])
+    assert (ranks == oranks).all()
+    st.close(); mesh.close()
+
+
+def test_channel_boundaries_fp64(ctx):
+    m, cfg = small_channel()
+    m0 = synth.initial_macros(cfg, m)
+    mesh, st = gpu_state(ctx, m, cfg, m0)
+    S = fv.Setup(m, cfg, m0)
+    ref_states = td.run(S, m0, 4)
+    st.step(4)
+    err, _ = macro_rel_err(st.moments(), oracle_macros(S, ref_states))
+    print(f"channel FP64 4 steps max rel macro err {err:.3e}")
+    assert err < 1e-10, err
+    compare_states(st, S, ref_states, cfg["N"], range(m["n_cells"]), 1e-10)
+    st.close(); mesh.close()
+
+
+def test_channel_mixed_precision(ctx):
+    m, cfg = small_channel(N=32, cap=12, tol=1e-5, precision="mixed")
+    m0 = synth.initial_macros(cfg, m)
+    mesh, st = gpu_state(ctx, m, cfg, m0)
+    S = fv.Setup(m, cfg, m0)
+    ref_states = td.run(S, m0, 3)
+    st.step(3)
+    err, _ = macro_rel_err(st.moments(), oracle_macros(S, ref_states))
+    print(f"channel mixed N=32 3 steps max rel macro err {err:.3e}")
+    assert err < 1e-5, err
+    st.close(); mesh.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_plain_step_matches_full_update(ctx, precision, tol):
+    m, cfg = small_channel(precision=precision)
+    m0 = synth.initial_macros(cfg, m)
+    mesh = tk.Mesh(ctx, m)
+    st = tk.State(ctx, mesh, cfg, m0, plain=True)
+    st.step(1)
+    got = st.moments()
+    S = fv.Setup(m, cfg, m0)
+    F = dvm.initial_full(S, m0)
+    ref = []
+    for i in range(m["n_cells"]):
+        X = dvm.update_full(S, i, lambda c: F[c])
+        n, u, T, q = kin.macros_full(X, S.xi, S.dxi)
+        ref.append([n, *u, T, *q])
+    err, _ = macro_rel_err(got, np.array(ref))
+    print(f"plain {precision} 1 step max rel macro err {err:.3e}")
+    assert err < tol, err
+    st.close(); mesh.close()
