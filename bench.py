@@ -1,0 +1,283 @@
+"""Throughput of the Tucker S-model step on one MI355X.
+
+Workload (default): the channel flow with an obstacle -- 64x32x32 lattice
+minus an 8^3 obstacle (65,024 hex cells), Mach-2 inflow, zero-gradient
+outflow, symmetry sides, diffuse walls at T_w = 1; velocity grid 32^3 on
+[-6, 6]^3; rank cap 12, rounding tolerance 1e-5; mixed precision (FP32
+term assembly, FP64 Gram/eigen/projection/moments).  A step is one pass of
+the whole hot path over every cell: moments, f_S, boundary ghosts, flux
+terms, truncated-HOSVD rounding.  Inputs are resident in HBM before the
+timed region; the timed region is `--steps` steps from the initial state
+after `--warmup` steps on a scratch state.
+
+One JSON line on stdout:  metric/value (cell-updates/s), roofline of the
+dominant kernel family (HIP events on the library stream), the plain
+full-tensor GPU step on the same workload, a sampled parity check against
+the FP64 oracle and the oracle's own CPU throughput (`cpu_baseline`).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from paper_1912_04582_amd import tk  # noqa: E402
+
+PEAK = {"fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "fp32_vec_nopk": 78.6e12, "fp64_vec": 78.6e12,
+        "hbm": 8.0e12}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    cfg = synth.make_config(name)
+    mesh = synth.configs.make_mesh(cfg)
+    return cfg, mesh, synth.initial_macros(cfg, mesh)
+
+
+def gram_flops(N, cells):
+    # symmetric mode Grams: 3 modes x N(N+1)/2 entries x N^2 products x 2
+    return cells * 3.0 * N * (N + 1) / 2 * N * N * 2
+
+
+def expand_flops(N, ranks, nb_ranks):
+    """Mode-product flops of the term assembly for cells with the given ranks.
+
+    Per source (the cell, its six far sides) 2 (r1 r2 r3 N + r1 r2 N^2 + r1 N^3),
+    plus the rank-4 f_S; boundary sides count as the cell's own ranks.
+    """
+    def src(r):
+        r = np.asarray(r, dtype=np.float64)
+        return 2 * (r[..., 0] * r[..., 1] * r[..., 2] * N + r[..., 0] * r[..., 1] * N * N + r[..., 0] * N ** 3)
+    return float(src(ranks).sum() + src(nb_ranks).sum() + ranks.shape[0] * src(np.array([4, 4, 4])))
+
+
+def neighbour_ranks(mesh, ranks):
+    fl, fr = mesh["face_left"], mesh["face_right"]
+    out = []
+    inner = fr >= 0
+    out.append(ranks[fr[inner]])      # far side of the left cells
+    out.append(ranks[fl[inner]])      # far side of the right cells
+    out.append(ranks[fl[~inner]])     # boundary ghosts: the cell's own ranks (upper bound)
+    return np.concatenate(out)
+
+
+def eig_flops(N, matrices):
+    # nominal dense symmetric eigensolver with vectors: 9 N^3 per matrix
+    return matrices * 9.0 * N ** 3
+
+
+def project_flops(N, ranks):
+    r = np.asarray(ranks, dtype=np.float64)
+    r1, r2, r3 = r[:, 0], r[:, 1], r[:, 2]
+    return float((2 * (r1 * N ** 3 + r1 * r2 * N * N + r1 * r2 * r3 * N)).sum())
+
+
+def roofline(fam, cfg, mesh, res, steps):
+    """Achieved rate of one kernel family against its bound, per launch."""
+    N, nc = cfg["N"], mesh["n_cells"]
+    ms, launches = res["prof"][fam]
+    per_launch_s = ms / 1e3 / launches
+    launches_per_step = launches / steps
+    r_avg = 0.5 * (res["ranks0"].astype(np.float64) + res["ranks1"].astype(np.float64))
+    if fam == "gram":
+        work, bound, peak, unit = gram_flops(N, nc), "mfma", PEAK["fp64_mfma"], "TFLOP/s"
+    elif fam == "eig":
+        work, bound, peak, unit = eig_flops(N, 3 * nc), "alu", PEAK["fp64_vec"], "TFLOP/s"
+    elif fam == "expand":
+        work = expand_flops(N, r_avg, neighbour_ranks(mesh, r_avg))
+        bound, peak, unit = "alu", PEAK["fp32_vec_nopk"], "TFLOP/s"
+    elif fam == "project":
+        work, bound, peak, unit = project_flops(N, r_avg), "alu", PEAK["fp64_vec"], "TFLOP/s"
+    else:
+        return None
+    achieved = work / launches_per_step / per_launch_s / 1e12
+    return {"bound": bound, "achieved": achieved, "peak": peak / 1e12, "unit": unit,
+            "frac": achieved / (peak / 1e12), "traffic": None, "kernel": fam,
+            "avg_launch_ms": per_launch_s * 1e3, "launches_per_step": launches_per_step}
+
+
+def sample_targets(mesh, count=12, seed=0):
+    """Cells next to each boundary kind plus random interior cells."""
+    fr, fl = mesh["face_right"], mesh["face_left"]
+    picks = []
+    for b in range(len(mesh["bc"])):
+        cand = fl[fr == -(b + 1)]
+        if cand.shape[0]:
+            picks.append(int(cand[cand.shape[0] // 2]))
+    rng = np.random.default_rng(seed)
+    while len(picks) < count:
+        picks.append(int(rng.integers(mesh["n_cells"])))
+    return sorted(set(picks))[:count]
+
+
+def cpu_leg(name, targets, steps):
+    """Oracle (O2) dependency cones of `targets` advanced `steps` steps; prints JSON."""
+    from oracle import fv, tucker_dvm as td
+    cfg, mesh, m0 = workload(name)
+    t0 = time.perf_counter()
+    S = fv.Setup(mesh, cfg, m0)
+    levels = td.cone(S, targets, steps)
+    st = td.run_cone(S, m0, targets, steps)
+    t1 = time.perf_counter()
+    updates = sum(len(l) for l in levels[1:])
+    macros = {int(i): td.macros_of(S, st[i]).tolist() for i in targets}
+    print(json.dumps({"seconds": t1 - t0, "updates": updates, "macros": macros,
+                      "levels": [len(l) for l in levels]}))
+
+
+def run_cpu_leg(name, targets, steps):
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", "--workload", name,
+           "--targets", ",".join(map(str, targets)), "--leg-steps", str(steps)]
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def gpu_macros_after(cfg, mesh, m0, steps):
+    ctx = tk.Context(0)
+    try:
+        tm = tk.Mesh(ctx, mesh)
+        st = tk.State(ctx, tm, cfg, m0)
+        st.step(steps)
+        out = st.moments()
+        st.close()
+        tm.close()
+    finally:
+        ctx.close()
+    return out
+
+
+def macro_rel_err(a, b, Rg=0.5, m=1.0):
+    a, b = np.asarray(a), np.asarray(b)
+    n, T = b[:, 0], b[:, 4]
+    c = np.sqrt(2 * Rg * T)
+    p = m * n * Rg * T
+    e = max(np.abs(a[:, 0] / n - 1).max(), np.abs(a[:, 4] / T - 1).max(),
+            (np.abs(a[:, 1:4] - b[:, 1:4]).max(1) / c).max(),
+            (np.abs(a[:, 5:8] - b[:, 5:8]).max(1) / (p * c)).max())
+    return float(e)
+
+
+def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True):
+    ctx = tk.Context(0)
+    try:
+        tm = tk.Mesh(ctx, mesh)
+        if warmup:
+            w = tk.State(ctx, tm, cfg, m0, plain=plain)
+            w.step(warmup)
+            w.close()
+        st = tk.State(ctx, tm, cfg, m0, plain=plain)
+        ctx.sync()
+        ctx.prof_reset()
+        ctx.prof_enable(prof)
+        r0 = None if plain else st.ranks()[0]
+        t0 = time.perf_counter()
+        st.step(steps)  # waits for completion
+        t1 = time.perf_counter()
+        ctx.prof_enable(False)
+        fams = ["moments", "expand", "gram", "eig", "project"] if not plain else ["plain_moments", "plain_step"]
+        prof_ms = {f: ctx.prof_get(f) for f in fams}
+        r1, C = (None, None) if plain else st.ranks()
+        st.close()
+        tm.close()
+    finally:
+        ctx.close()
+    return dict(seconds=t1 - t0, prof=prof_ms, ranks0=r0, ranks1=r1, compression=C)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg1")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=50)
+    ap.add_argument("--parity-steps", type=int, default=3)
+    ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--targets", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--leg-steps", type=int, default=2, help=argparse.SUPPRESS)
+    a = ap.parse_args()
+    if a.cpu_leg:
+        cpu_leg(a.workload, [int(x) for x in a.targets.split(",")], a.leg_steps)
+        return
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    cfg, mesh, m0 = workload(a.workload)
+    nc = mesh["n_cells"]
+    N = cfg["N"]
+    log(f"workload {cfg['name']}: {nc} cells, N={N}, cap {cfg['cap']}, tol {cfg['tol']}, {cfg['precision']}")
+    res = run_gpu(cfg, mesh, m0, a.steps, a.warmup)
+    ms_step = 1e3 * res["seconds"] / a.steps
+    value = nc * a.steps / res["seconds"]
+    log(f"tucker: {ms_step:.2f} ms/step, {value:.4g} cell-updates/s, mean compression {res['compression']:.4g}")
+    for f, (ms, n) in res["prof"].items():
+        log(f"  {f:10s} {ms:10.2f} ms total over {n} launches")
+    r1 = res["ranks1"]
+    rmax = r1.max(1)
+    log("  final max-rank histogram:", np.bincount(rmax, minlength=cfg["cap"] + 1).tolist())
+    nbr = neighbour_ranks(mesh, r1)
+    r0 = 2 * r1.astype(np.int64).sum(1)  # own [U, D U] columns summed over modes
+    log(f"  mean rank {r1.mean():.2f}")
+    fam, (fms, fn) = max(res["prof"].items(), key=lambda kv: kv[1][0])
+    roof = roofline(fam, cfg, mesh, res, a.steps)
+    log(f"  roofline ({fam}): {roof}")
+    plain = None
+    if not a.no_plain:
+        pres = run_gpu(cfg, mesh, m0, a.plain_steps, 1, plain=True)
+        pv = nc * a.plain_steps / pres["seconds"]
+        plain = {"value": pv, "unit": "cell-updates/s", "ms_per_step": 1e3 * pres["seconds"] / a.plain_steps,
+                 "steps": a.plain_steps, "storage": "N^3 values per cell",
+                 "kernel_ms_per_step": {f: ms / a.plain_steps for f, (ms, n) in pres["prof"].items()}}
+        log(f"plain: {plain['ms_per_step']:.2f} ms/step, {pv:.4g} cell-updates/s")
+    cpu = parity = None
+    if not a.no_cpu:
+        targets = sample_targets(mesh)
+        leg = run_cpu_leg(a.workload, targets, a.parity_steps)
+        cpu = {"value": leg["updates"] / leg["seconds"], "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"Tucker-form oracle, dependency cones of {len(targets)} cells advanced "
+                         f"{a.parity_steps} steps from the initial state ({leg['updates']} cell-updates, "
+                         f"{leg['seconds']:.1f} s, one thread)"}
+        g = gpu_macros_after(cfg, mesh, m0, a.parity_steps)
+        ref = np.array([leg["macros"][str(t)] for t in targets])
+        err = macro_rel_err(g[targets], ref)
+        bar = 1e-5 if cfg["precision"] == "mixed" else 1e-10
+        parity = {"max_rel_err": err, "bar": bar, "pass": bool(err <= bar), "cells": targets,
+                  "steps": a.parity_steps}
+        log(f"cpu oracle: {cpu['value']:.4g} cell-updates/s; parity after {a.parity_steps} steps: {err:.3e}")
+    out = {
+        "metric": "Tucker S-model cell-updates/s (vs plain GPU step at 1e-5 rel err)",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 terms + f64 rounding" if cfg["precision"] == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "cells": nc, "N": N, "rank_cap": cfg["cap"], "tol": cfg["tol"],
+                   "precision": cfg["precision"], "steps_from_init": a.steps},
+        "dominant_kernel": fam,
+        "kernel_ms_per_step": {f: ms / a.steps for f, (ms, n) in res["prof"].items()},
+        "mean_compression": res["compression"],
+        "roofline": roof,
+        "plain_gpu": plain,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
