@@ -224,6 +224,192 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
     for (int i = 0; i < N; ++i) out[(size_t)pf[f] * N + i] = acc[f][i];
 }
 
+// Same update with every source staged into LDS in one pass (one global-load
+// latency per cell instead of one per source); used when the worst-case
+// staging area fits the LDS.  Source 0 is the cell, 1 is f_S, 2..7 the far
+// sides of the six face slots.
+constexpr int kSrc = 8;
+
+template <int N, int BLOCK, typename T>
+__global__ __launch_bounds__(BLOCK) void k_expand_pf(DevState d, int c0, T* X) {
+  constexpr int FIB = N * N / BLOCK;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int CS = d.CS;
+  T* sxi = smem;                     // N
+  T* sd = sxi + N;                   // 3 N
+  T* sY = sd + 3 * N;                // KC CS N
+  T* sZ = sY + KC * CS * N;          // KC N N
+  T* pool = sZ + KC * N * N;         // kSrc (3 CS N + CS^3)
+  __shared__ int s_r[kSrc][3];
+  __shared__ int s_offU[kSrc], s_offG[kSrc], s_on[kSrc];
+  const int c = c0 + blockIdx.x;
+  const int tid = threadIdx.x;
+  const InstParams P = d.ip[d.inst[c]];
+  const double nu = d.nu[c];
+  int pf[FIB];
+#pragma unroll
+  for (int f = 0; f < FIB; ++f) pf[f] = tid + BLOCK * f;
+  if (tid == 0) {
+    int off = 0;
+    for (int s = 0; s < kSrc; ++s) {
+      int r1 = 0, r2 = 0, r3 = 0, on = 1;
+      if (s == 0) {
+        r1 = d.rank[3 * c]; r2 = d.rank[3 * c + 1]; r3 = d.rank[3 * c + 2];
+      } else if (s == 1) {
+        r1 = r2 = r3 = 4;
+      } else {
+        const int l = s - 2;
+        const int8_t kind = d.slot_kind[kSlots * c + l];
+        if (kind == SK_NONE) {
+          on = 0;
+        } else if (kind == SK_INTERIOR || kind == SK_OUTFLOW || kind == SK_SYM) {
+          const int src = (kind == SK_INTERIOR) ? d.slot_nb[kSlots * c + l] : c;
+          r1 = d.rank[3 * src]; r2 = d.rank[3 * src + 1]; r3 = d.rank[3 * src + 2];
+        } else {
+          r1 = r2 = r3 = 1;
+        }
+      }
+      s_r[s][0] = r1; s_r[s][1] = r2; s_r[s][2] = r3; s_on[s] = on;
+      s_offU[s] = off;
+      off += 3 * CS * N;
+      s_offG[s] = off;
+      off += CS * CS * CS;
+    }
+  }
+  for (int i = tid; i < N; i += BLOCK) {
+    const double x = P.xi_min + i * P.dxi;
+    sxi[i] = (T)x;
+    for (int a = 0; a < 3; ++a) {
+      double sum = 0.0;
+      for (int l = 0; l < kSlots; ++l) {
+        const int8_t kind = d.slot_kind[kSlots * c + l];
+        if (kind == SK_NONE || d.slot_axis[kSlots * c + l] != a) continue;
+        sum -= d.slot_coef[kSlots * c + l] * fmax((double)d.slot_sig[kSlots * c + l] * x, 0.0);
+      }
+      sd[a * N + i] = (T)sum;
+    }
+  }
+  __syncthreads();
+  // ---- stage every source --------------------------------------------------
+  for (int s = 0; s < kSrc; ++s) {
+    if (!s_on[s]) continue;
+    T* sU = pool + s_offU[s];
+    T* sG = pool + s_offG[s];
+    const int r1 = s_r[s][0], r2 = s_r[s][1], r3 = s_r[s][2];
+    if (s == 1) {
+      // f_S in Tucker form, scaled by dt nu
+      const double* M = d.macro + 8 * (size_t)c;
+      const double n = M[0], T0 = M[4];
+      const double RT = P.Rg * T0;
+      const double amp = cbrt(n) / sqrt(2.0 * M_PI * RT);
+      const double beta = 1.0 / (2.0 * RT);
+      const double As = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * n * RT * RT);
+      for (int o = tid; o < 3 * N; o += BLOCK) {
+        const int a = o / N, i = o % N;
+        const double v = P.xi_min + i * P.dxi - M[1 + a];
+        const double base = amp * exp(-v * v * beta);
+        sU[a * CS * N + 0 * N + i] = (T)base;
+        sU[a * CS * N + 1 * N + i] = (T)(base * v);
+        sU[a * CS * N + 2 * N + i] = (T)(base * v * v);
+        sU[a * CS * N + 3 * N + i] = (T)(base * v * v * v);
+      }
+      if (tid < 64) {
+        // 4x4x4 core: 1, v_a, v_a^3 and v_a v_b^2 monomials
+        const int o = tid, k1 = o & 3, k2 = (o >> 2) & 3, k3 = o >> 4;
+        const int k[3] = {k1, k2, k3};
+        const double sc = P.dt * nu;
+        double g = 0.0;
+        int nz = 0, which = -1;
+        for (int a = 0; a < 3; ++a)
+          if (k[a]) { ++nz; which = a; }
+        if (nz == 0) {
+          g = 1.0;
+        } else if (nz == 1) {
+          const double qa = M[5 + which];
+          if (k[which] == 1) g = -2.5 * As * qa;
+          else if (k[which] == 3) g = As * beta * qa;
+        } else if (nz == 2) {
+          // v_a v_b^2 with a != b
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+              if (a != b && k[a] == 1 && k[b] == 2 && k[3 - a - b] == 0) g = As * beta * M[5 + a];
+        }
+        sG[o] = (T)(sc * g);
+      }
+      continue;
+    }
+    int src = c, rev = -1, ax = -1, bc = -1;
+    double coef = 0.0, sg = 0.0, gsc = 1.0;
+    if (s >= 2) {
+      const int l = s - 2;
+      const int8_t kind = d.slot_kind[kSlots * c + l];
+      ax = d.slot_axis[kSlots * c + l];
+      sg = (double)d.slot_sig[kSlots * c + l];
+      coef = d.slot_coef[kSlots * c + l];
+      const int nb = d.slot_nb[kSlots * c + l];
+      if (kind == SK_INTERIOR) src = nb;
+      if (kind == SK_SYM) rev = ax;
+      if (kind == SK_INFLOW || kind == SK_WALL) {
+        bc = nb;
+        if (kind == SK_WALL) gsc = d.nw[kSlots * c + l];
+      }
+    }
+    if (bc >= 0) {
+      const double* bf = d.bc_fac + (size_t)bc * 3 * N;
+      for (int o = tid; o < 3 * N; o += BLOCK) {
+        const int a = o / N, i = o % N;
+        double v = bf[o];
+        if (a == ax) v *= coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0);
+        sU[a * CS * N + i] = (T)v;
+      }
+      if (tid == 0) sG[0] = (T)gsc;
+      continue;
+    }
+    const int rr[3] = {r1, r2, r3};
+    for (int o = tid; o < 3 * CS * N; o += BLOCK) {
+      const int a = o / (CS * N), rem = o % (CS * N), k = rem / N, i = rem % N;
+      if (k >= rr[a]) continue;
+      const int is = (a == rev) ? (N - 1 - i) : i;
+      double v = d.fac[((size_t)src * 3 + a) * CS * N + k * N + is];
+      if (a == ax) v *= coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0);
+      sU[o] = (T)v;
+    }
+    for (int o = tid; o < r1 * r2 * r3; o += BLOCK) {
+      const int k1 = o % r1, t = o / r1, k2 = t % r2, k3 = t / r2;
+      sG[o] = (T)d.core[(size_t)src * CS * CS * CS + k1 + CS * (k2 + CS * k3)];
+    }
+  }
+  __syncthreads();
+  // ---- mode products, accumulated in registers --------------------------------
+  T acc[FIB][N];
+#pragma unroll
+  for (int f = 0; f < FIB; ++f)
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[f][i] = 0;
+  expand_source<N, BLOCK, T, FIB>(acc, pool + s_offU[0], pool + s_offG[0], sY, sZ, s_r[0][0], s_r[0][1],
+                                  s_r[0][2], CS, pf);
+  {
+    const T cterm = (T)(1.0 - P.dt * nu);
+#pragma unroll
+    for (int f = 0; f < FIB; ++f) {
+      const T dd = cterm + sd[N + pf[f] % N] + sd[2 * N + pf[f] / N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[f][i] *= (sd[i] + dd);
+    }
+  }
+  for (int s = 1; s < kSrc; ++s) {
+    if (!s_on[s]) continue;
+    expand_source<N, BLOCK, T, FIB>(acc, pool + s_offU[s], pool + s_offG[s], sY, sZ, s_r[s][0], s_r[s][1],
+                                    s_r[s][2], CS, pf);
+  }
+  T* out = X + (size_t)blockIdx.x * N * N * N;
+#pragma unroll
+  for (int f = 0; f < FIB; ++f)
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[(size_t)pf[f] * N + i] = acc[f][i];
+}
+
 // Plain expansion of state-layout Tucker tensors (rounding test hook).
 template <int N, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_expand_plain(int CS, const double* core, const double* fac,
@@ -266,6 +452,14 @@ template <int N, typename T>
 hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, hipStream_t s) {
   constexpr int B = ExpandShape<N>::B;
   const int CS = d.CS;
+  const size_t shp = sizeof(T) * (4 * N + KC * CS * N + KC * N * N + kSrc * (3 * CS * N + CS * CS * CS));
+  if (shp <= 120 * 1024) {
+    auto k = k_expand_pf<N, B, T>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shp);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(count), dim3(B), shp, s, d, c0, (T*)X);
+    return hipGetLastError();
+  }
   const size_t sh = sizeof(T) * (N + 3 * N + N + 3 * CS * N + CS * CS * CS + KC * CS * N + KC * N * N);
   hipLaunchKernelGGL((k_expand<N, B, T>), dim3(count), dim3(B), sh, s, d, c0, (T*)X);
   return hipGetLastError();

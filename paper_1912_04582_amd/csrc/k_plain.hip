@@ -88,56 +88,81 @@ __global__ __launch_bounds__(kPM) void k_plain_moments(DevPlain d) {
   }
 }
 
+// One thread updates EPT consecutive grid nodes of one cell; the per-cell
+// constants (f_S parameters, face coefficients) are computed once per
+// workgroup.  Reads the cell and its six far sides once per node.
 template <int N, typename T>
 __global__ __launch_bounds__(kPM) void k_plain_step(DevPlain d) {
   constexpr int NE = N * N * N;
+  constexpr int EPT = 4;
+  __shared__ double s_c[16];
+  __shared__ double s_coef[kSlots];
+  __shared__ int s_nb[kSlots];
+  __shared__ int8_t s_kind[kSlots], s_axis[kSlots], s_sig[kSlots];
   const int c = blockIdx.x;
-  const int e = blockIdx.y * kPM + threadIdx.x;
-  if (e >= NE) return;
   const InstParams P = d.ip[d.inst[c]];
-  const int idx[3] = {e % N, (e / N) % N, e / (N * N)};
-  const double x[3] = {P.xi_min + idx[0] * P.dxi, P.xi_min + idx[1] * P.dxi, P.xi_min + idx[2] * P.dxi};
-  const T* f = (const T*)d.f;
-  const double* M = d.macro + 8 * (size_t)c;
-  const double nu = d.nu[c];
-  const double own = (double)f[(size_t)c * NE + e];
-  // f_S at this node
-  const double RT = P.Rg * M[4];
-  const double v[3] = {x[0] - M[1], x[1] - M[2], x[2] - M[3]};
-  const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-  const double fm = M[0] / pow(2.0 * M_PI * RT, 1.5) * exp(-v2 / (2.0 * RT));
-  const double As = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * M[0] * RT * RT);
-  const double qv = M[5] * v[0] + M[6] * v[1] + M[7] * v[2];
-  const double fs = fm * (1.0 + As * qv * (v2 / (2.0 * RT) - 2.5));
-  double w = 1.0 - P.dt * nu;
-  double acc = P.dt * nu * fs;
-  for (int l = 0; l < kSlots; ++l) {
-    const int8_t kind = d.slot_kind[kSlots * c + l];
-    if (kind == SK_NONE) continue;
-    const int a = d.slot_axis[kSlots * c + l];
-    const double sg = (double)d.slot_sig[kSlots * c + l];
-    const double coef = d.slot_coef[kSlots * c + l];
-    w -= coef * fmax(sg * x[a], 0.0);
-    const double b = coef * fmax(-sg * x[a], 0.0);
-    if (b == 0.0) continue;
-    const int nb = d.slot_nb[kSlots * c + l];
-    double g;
-    if (kind == SK_INTERIOR) {
-      g = (double)f[(size_t)nb * NE + e];
-    } else if (kind == SK_OUTFLOW) {
-      g = own;
-    } else if (kind == SK_SYM) {
-      int r[3] = {idx[0], idx[1], idx[2]};
-      r[a] = N - 1 - r[a];
-      g = (double)f[(size_t)c * NE + r[0] + N * (r[1] + N * r[2])];
-    } else {
-      const double* bf = d.bc_fac + (size_t)nb * 3 * N;
-      g = bf[idx[0]] * bf[N + idx[1]] * bf[2 * N + idx[2]];
-      if (kind == SK_WALL) g *= d.nw[kSlots * c + l];
+  if (threadIdx.x == 0) {
+    const double* M = d.macro + 8 * (size_t)c;
+    const double nu = d.nu[c];
+    const double RT = P.Rg * M[4];
+    s_c[0] = M[0] / pow(2.0 * M_PI * RT, 1.5);               // f_M amplitude
+    s_c[1] = 1.0 / (2.0 * RT);                               // 1 / (2 R_g T)
+    s_c[2] = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * M[0] * RT * RT);  // A_s
+    s_c[3] = P.dt * nu;
+    for (int a = 0; a < 3; ++a) { s_c[4 + a] = M[1 + a]; s_c[7 + a] = M[5 + a]; }
+    for (int l = 0; l < kSlots; ++l) {
+      s_kind[l] = d.slot_kind[kSlots * c + l];
+      s_axis[l] = d.slot_axis[kSlots * c + l];
+      s_sig[l] = d.slot_sig[kSlots * c + l];
+      s_coef[l] = d.slot_coef[kSlots * c + l];
+      s_nb[l] = d.slot_nb[kSlots * c + l];
     }
-    acc += b * g;
   }
-  ((T*)d.f_n)[(size_t)c * NE + e] = (T)(w * own + acc);
+  __syncthreads();
+  const int e0 = (blockIdx.y * kPM + threadIdx.x) * EPT;
+  if (e0 >= NE) return;
+  const T* f = (const T*)d.f;
+  const double amp = s_c[0], ib = s_c[1], As = s_c[2], dtnu = s_c[3];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = e0 + q;
+    const int idx[3] = {e % N, (e / N) % N, e / (N * N)};
+    const double x[3] = {P.xi_min + idx[0] * P.dxi, P.xi_min + idx[1] * P.dxi, P.xi_min + idx[2] * P.dxi};
+    const double own = (double)f[(size_t)c * NE + e];
+    const double v[3] = {x[0] - s_c[4], x[1] - s_c[5], x[2] - s_c[6]};
+    const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double qv = s_c[7] * v[0] + s_c[8] * v[1] + s_c[9] * v[2];
+    const double fs = amp * exp(-v2 * ib) * (1.0 + As * qv * (v2 * ib - 2.5));
+    double w = 1.0 - dtnu;
+    double acc = dtnu * fs;
+    for (int l = 0; l < kSlots; ++l) {
+      const int8_t kind = s_kind[l];
+      if (kind == SK_NONE) continue;
+      const int a = s_axis[l];
+      const double sg = (double)s_sig[l];
+      const double coef = s_coef[l];
+      w -= coef * fmax(sg * x[a], 0.0);
+      const double b = coef * fmax(-sg * x[a], 0.0);
+      if (b == 0.0) continue;
+      const int nb = s_nb[l];
+      double g;
+      if (kind == SK_INTERIOR) {
+        g = (double)f[(size_t)nb * NE + e];
+      } else if (kind == SK_OUTFLOW) {
+        g = own;
+      } else if (kind == SK_SYM) {
+        int r[3] = {idx[0], idx[1], idx[2]};
+        r[a] = N - 1 - r[a];
+        g = (double)f[(size_t)c * NE + r[0] + N * (r[1] + N * r[2])];
+      } else {
+        const double* bf = d.bc_fac + (size_t)nb * 3 * N;
+        g = bf[idx[0]] * bf[N + idx[1]] * bf[2 * N + idx[2]];
+        if (kind == SK_WALL) g *= d.nw[kSlots * c + l];
+      }
+      acc += b * g;
+    }
+    ((T*)d.f_n)[(size_t)c * NE + e] = (T)(w * own + acc);
+  }
 }
 
 template <int N, typename T>
@@ -228,7 +253,7 @@ hipError_t launch_plain_moments(const DevPlain& d, int mixed, hipStream_t s) {
 hipError_t launch_plain_step(const DevPlain& d, int mixed, hipStream_t s) {
   if (d.n_cells == 0) return hipSuccess;
   const int ne = d.N * d.N * d.N;
-  dim3 grid(d.n_cells, (ne + kPM - 1) / kPM);
+  dim3 grid(d.n_cells, (ne + 4 * kPM - 1) / (4 * kPM));
   TK_PLAIN_DISPATCH(k_plain_step, grid, dim3(kPM), d);
   return hipGetLastError();
 }

@@ -78,9 +78,75 @@ __global__ __launch_bounds__(kProjThreads) void k_project(const T* X, int c0, in
   }
 }
 
+// Variant for tensors whose first mode product fits the LDS: every thread
+// reads whole mode-1 fibres (N contiguous values, coalesced across the
+// workgroup) once, Y1 = W1^T A is kept in LDS, then Y2 = Y1 x2 W2^T and
+// C = Y2 x3 W3^T; two barriers in total.
+template <int N, typename T>
+__global__ __launch_bounds__(kProjThreads) void k_project_fib(const T* X, int c0, int CS, const double* fac_n,
+                                                             const int* rank_n, double* core_n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* sW = reinterpret_cast<double*>(smem_raw);  // 3 CS N
+  double* sY2 = sW + 3 * CS * N;                     // CS CS N
+  T* sY1 = reinterpret_cast<T*>(sY2 + CS * CS * N);  // CS N^2
+  const int cl = blockIdx.x;
+  const int cell = c0 + cl;
+  const int tid = threadIdx.x;
+  const int r1 = rank_n[3 * cell], r2 = rank_n[3 * cell + 1], r3 = rank_n[3 * cell + 2];
+  for (int o = tid; o < 3 * CS * N; o += kProjThreads) sW[o] = fac_n[(size_t)cell * 3 * CS * N + o];
+  __syncthreads();
+  const T* x = X + (size_t)cl * N * N * N;
+  const double* W1 = sW;
+  const double* W2 = sW + CS * N;
+  const double* W3 = sW + 2 * CS * N;
+  for (int p = tid; p < N * N; p += kProjThreads) {
+    T f[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) f[i] = x[(size_t)p * N + i];
+    for (int k1 = 0; k1 < r1; ++k1) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) s += W1[k1 * N + i] * (double)f[i];
+      sY1[k1 * N * N + p] = (T)s;
+    }
+  }
+  __syncthreads();
+  // Y2[k1][k2][i3] = sum_i2 W2[k2][i2] Y1[k1][i2 + N i3]
+  for (int o = tid; o < r1 * r2 * N; o += kProjThreads) {
+    const int i3 = o % N, t = o / N, k2 = t % r2, k1 = t / r2;
+    double s = 0.0;
+    for (int i2 = 0; i2 < N; ++i2) s += W2[k2 * N + i2] * (double)sY1[k1 * N * N + i2 + N * i3];
+    sY2[(k1 * r2 + k2) * N + i3] = s;
+  }
+  __syncthreads();
+  double* out = core_n + (size_t)cell * CS * CS * CS;
+  for (int o = tid; o < CS * CS * CS; o += kProjThreads) {
+    const int k1 = o % CS, t = o / CS, k2 = t % CS, k3 = t / CS;
+    double s = 0.0;
+    if (k1 < r1 && k2 < r2 && k3 < r3) {
+      const double* y = sY2 + (k1 * r2 + k2) * N;
+      for (int i3 = 0; i3 < N; ++i3) s += W3[k3 * N + i3] * y[i3];
+    }
+    out[o] = s;
+  }
+}
+
+template <int N, typename T>
+size_t project_fib_bytes(int CS) {
+  return sizeof(double) * (3 * (size_t)CS * N + (size_t)CS * CS * N) + sizeof(T) * (size_t)CS * N * N;
+}
+
 template <int N, typename T>
 hipError_t launch_project_t(int count, const void* X, int c0, int CS, const double* fac_n, const int* rank_n,
                             double* core_n, hipStream_t s) {
+  const size_t shf = project_fib_bytes<N, T>(CS);
+  if (shf <= 96 * 1024) {
+    auto k = k_project_fib<N, T>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shf);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(count), dim3(kProjThreads), shf, s, (const T*)X, c0, CS, fac_n, rank_n, core_n);
+    return hipGetLastError();
+  }
   const size_t sh = sizeof(double) * (N * N + 3 * CS * N + CS * N + CS * CS);
   hipLaunchKernelGGL((k_project<N, T>), dim3(count), dim3(kProjThreads), sh, s, (const T*)X, c0, CS, fac_n,
                      rank_n, core_n);

@@ -434,6 +434,7 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     if (!S->X) { state_free(S); return s; }
     ALLOC(G, double, (size_t)S->chunk * 3 * N * N);
     if (!S->mixed) ALLOC(Wb, double, (size_t)S->chunk * 3 * N * N);
+    ALLOC(Wkeep, double, (size_t)nc * 3 * N * N);
   }
 #undef ALLOC
   hipStream_t q = ctx->stream;
@@ -467,6 +468,7 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
       if (e == hipSuccess) e = hipMemsetAsync(S->rank[b], 0, sizeof(int) * (size_t)nc * 3, q);
     }
     if (e == hipSuccess) e = launch_init_maxwell(state_dev(S), S->d_macro5, q);
+    if (e == hipSuccess) e = launch_identity_basis(N, (size_t)nc * 3, S->Wkeep, q);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(q);
   if (e != hipSuccess) { state_free(S); return ctx_hip(ctx, e, "state init"); }
@@ -511,15 +513,15 @@ static tk_status state_step_once(tk_state* st) {
     prof_begin(ctx, KID_EIG, &ev);
     if (st->mixed) {
       e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
-                     nullptr, q);
+                     nullptr, st->Wkeep, 1e-12, 1e-16, q);
     } else {
       // FP64 path: first basis, Gram of the rotated unfoldings, final basis
       e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
-                     st->Wb, q);
+                     st->Wb, st->Wkeep, 1e-15, 1e-18, q);
       if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, st->X, 0, st->Wb, st->G, q);
       if (e == hipSuccess)
         e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, st->Wb,
-                       nullptr, q);
+                       nullptr, nullptr, 1e-15, 1e-18, q);
     }
     prof_end(ctx, KID_EIG, ev);
     if (e != hipSuccess) return ctx_hip(ctx, e, "eig");
@@ -855,9 +857,9 @@ tk_status tk_round_tucker(tk_ctx* ctx, int32_t count, const tk_tucker* in, doubl
   if (e == hipSuccess) e = hipMemcpyAsync(d_rk, rk.data(), sizeof(int) * rk.size(), hipMemcpyHostToDevice, q);
   if (e == hipSuccess) e = launch_expand_plain(N, count, CSi, d_core, d_fac, d_rk, d_X, q);
   if (e == hipSuccess) e = launch_gram(N, count, d_X, 0, d_G, q);
-  if (e == hipSuccess) e = launch_eig(N, count, d_G, nullptr, nullptr, 0, tol, cap, CSo, d_fo, d_ro, nullptr, d_W, q);
+  if (e == hipSuccess) e = launch_eig(N, count, d_G, nullptr, nullptr, 0, tol, cap, CSo, d_fo, d_ro, nullptr, d_W, nullptr, 1e-15, 1e-18, q);
   if (e == hipSuccess) e = launch_gram_rot(N, count, d_X, 0, d_W, d_G, q);
-  if (e == hipSuccess) e = launch_eig(N, count, d_G, nullptr, nullptr, 0, tol, cap, CSo, d_fo, d_ro, d_W, nullptr, q);
+  if (e == hipSuccess) e = launch_eig(N, count, d_G, nullptr, nullptr, 0, tol, cap, CSo, d_fo, d_ro, d_W, nullptr, nullptr, 1e-15, 1e-18, q);
   if (e == hipSuccess) e = launch_project(N, count, d_X, 0, 0, CSo, d_fo, d_ro, d_co, q);
   std::vector<double> co((size_t)count * CSo * CSo * CSo), fo((size_t)count * 3 * CSo * N);
   std::vector<int> ro((size_t)count * 3);

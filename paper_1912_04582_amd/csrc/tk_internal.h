@@ -79,7 +79,10 @@ hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hi
 // inst == nullptr)
 hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
                       double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
-                      const double* Win, double* Wout, hipStream_t s);
+                      const double* Win, double* Wout, double* Wkeep, double rel_thr, double abs_fac,
+                      hipStream_t s);
+// set `count` N x N bases to the identity (cold start of the warm-started eigensolver)
+hipError_t launch_identity_basis(int N, size_t count, double* W, hipStream_t s);
 // Gram of the rotated unfoldings: G2_a = (W_a^T A_(a)) (W_a^T A_(a))^T
 hipError_t launch_gram_rot(int N, int count, const void* X, int mixed, const double* W, double* G2,
                            hipStream_t s);

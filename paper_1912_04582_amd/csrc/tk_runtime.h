@@ -78,7 +78,8 @@ struct tk_state {
   // rounding workspaces
   void* X = nullptr;
   double* G = nullptr;
-  double* Wb = nullptr;  // first-pass bases of the FP64 refinement
+  double* Wb = nullptr;     // first-pass bases of the FP64 refinement
+  double* Wkeep = nullptr;  // [nc][3][N][N] previous full eigenbases (warm start)
   // plain comparator storage
   void* pf[2] = {nullptr, nullptr};
 };
