@@ -198,6 +198,47 @@ def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True):
     return dict(seconds=t1 - t0, prof=prof_ms, ranks0=r0, ranks1=r1, compression=C)
 
 
+def run_batch(steps, warmup, count):
+    """The batched workload: independent periodic boxes grouped by N into
+    one state per N; every state advances `steps` steps."""
+    insts = synth.configs.batch_instances(count=count)
+    groups = {}
+    for c in insts:
+        m = synth.configs.make_mesh(c)
+        groups.setdefault(c["N"], []).append((c, m, synth.initial_macros(c, m)))
+    ctx = tk.Context(0)
+    try:
+        states, meshes = [], []
+        for N, items in sorted(groups.items()):
+            ms = [tk.Mesh(ctx, m) for _, m, _ in items]
+            meshes += ms
+            if warmup:
+                # a small state of the group's first instance loads the kernels
+                w = tk.State(ctx, ms[:1], [items[0][0]], [items[0][2]])
+                w.step(warmup)
+                w.close()
+            states.append(tk.State(ctx, ms, [c for c, _, _ in items], [m0 for _, _, m0 in items]))
+        cells = sum(s.n_cells for s in states)
+        ctx.sync()
+        ctx.prof_reset()
+        ctx.prof_enable(True)
+        t0 = time.perf_counter()
+        for st in states:
+            st.step_async(steps)
+        ctx.sync()
+        t1 = time.perf_counter()
+        ctx.prof_enable(False)
+        prof = {f: ctx.prof_get(f) for f in ["moments", "expand", "gram", "eig", "project"]}
+        for st in states:
+            st.close()
+        for m in meshes:
+            m.close()
+    finally:
+        ctx.close()
+    return dict(seconds=t1 - t0, cells=cells, prof=prof,
+                groups={N: (len(v), sum(m["n_cells"] for _, m, _ in v)) for N, v in groups.items()})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +249,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--parity-steps", type=int, default=3)
+    ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--targets", default="", help=argparse.SUPPRESS)
     ap.add_argument("--leg-steps", type=int, default=2, help=argparse.SUPPRESS)
@@ -218,6 +260,23 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if a.workload == "batch":
+        steps = a.steps if a.steps != 200 else 50
+        r = run_batch(steps, a.warmup, a.batch_count)
+        value = r["cells"] * steps / r["seconds"]
+        log(f"batch: {r['cells']} cells in {a.batch_count} instances {r['groups']}, "
+            f"{1e3 * r['seconds'] / steps:.2f} ms/step, {value:.4g} cell-updates/s")
+        for f, (ms, n) in r["prof"].items():
+            log(f"  {f:10s} {ms:10.2f} ms total over {n} launches")
+        print(json.dumps({
+            "metric": "Tucker S-model cell-updates/s (vs plain GPU step at 1e-5 rel err)", "value": value,
+            "unit": "cell-updates/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup,
+            "ms_per_step": 1e3 * r["seconds"] / steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32 terms + f64 rounding", "data": "synthetic",
+            "config": {"workload": f"batch of {a.batch_count} periodic boxes", "cells": r["cells"],
+                       "groups_by_N": {str(k): v for k, v in r["groups"].items()}},
+            "kernel_ms_per_step": {f: ms / steps for f, (ms, n) in r["prof"].items()}}), flush=True)
+        return
     cfg, mesh, m0 = workload(a.workload)
     nc = mesh["n_cells"]
     N = cfg["N"]

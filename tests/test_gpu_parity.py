@@ -184,3 +184,71 @@ def test_plain_step_matches_full_update(ctx, precision, tol):
     print(f"plain {precision} 1 step max rel macro err {err:.3e}")
     assert err < tol, err
     st.close(); mesh.close()
+
+
+def test_batch_equals_alone_and_oracle(ctx):
+    """Instances advanced together give the same result as each alone."""
+    specs = []
+    m1, c1 = small_channel(N=16, cap=5, tol=1e-6)
+    specs.append((m1, c1))
+    m2 = synth.periodic_box(3)
+    c2 = dict(c1, cap=4, tol=1e-5, Kn=0.3, seed=21)
+    specs.append((m2, c2))
+    m3 = synth.periodic_box(4, length=0.5)
+    c3 = dict(c1, cap=6, tol=1e-7, Kn=0.05, seed=22, xi_max=5.0)
+    specs.append((m3, c3))
+    macros = [synth.initial_macros(c, m) for m, c in specs]
+    meshes = [tk.Mesh(ctx, m) for m, _ in specs]
+    batch = tk.State(ctx, meshes, [c for _, c in specs], macros)
+    res = batch.step(4, residual=True)
+    got = batch.moments()
+    batch.close()
+    off = 0
+    for (m, c), mesh, m0 in zip(specs, meshes, macros):
+        alone = tk.State(ctx, mesh, c, m0)
+        alone.step(4)
+        a = alone.moments()
+        alone.close()
+        part = got[off:off + m["n_cells"]]
+        assert np.array_equal(part, a), np.abs(part - a).max()
+        off += m["n_cells"]
+    # the second instance against the oracle
+    S = fv.Setup(m2, c2, macros[1])
+    ref = oracle_macros(S, td.run(S, macros[1], 4))
+    err, _ = macro_rel_err(got[specs[0][0]["n_cells"]:specs[0][0]["n_cells"] + m2["n_cells"]], ref)
+    assert err < 1e-10, err
+    assert res.shape == (3,) and np.all(res > 0)
+    for mesh in meshes:
+        mesh.close()
+
+
+def test_uniform_state_stays_rank1_on_gpu(ctx):
+    cfg = synth.make_config("cfg0", init="uniform")
+    m = synth.configs.make_mesh(cfg)
+    m0 = synth.initial_macros(cfg, m)
+    mesh, st = gpu_state(ctx, m, cfg, m0)
+    first = st.moments()
+    st.step(20)
+    last = st.moments()
+    r, C = st.ranks()
+    assert (r == 1).all()
+    assert np.abs(last[:, 0] / first[:, 0] - 1).max() < 1e-9
+    assert np.abs(last[:, 4] / first[:, 4] - 1).max() < 1e-9
+    assert np.abs(last[:, 1:4]).max() < 1e-13 and np.abs(last[:, 5:]).max() < 1e-13
+    st.close(); mesh.close()
+
+
+def test_invalid_arguments_rejected(ctx):
+    m, cfg = small_channel()
+    m0 = synth.initial_macros(cfg, m)
+    mesh = tk.Mesh(ctx, m)
+    for bad in (dict(N=20), dict(cap=17), dict(cap=0), dict(tol=-1.0), dict(precision="fp64", N=48)):
+        with pytest.raises(tk.TkError) as ei:
+            tk.State(ctx, mesh, dict(cfg, **bad), m0)
+        assert ei.value.status == tk.TK_EINVAL
+    neg = m0.copy()
+    neg[3, 4] = -1.0
+    with pytest.raises(tk.TkError) as ei:
+        tk.State(ctx, mesh, cfg, neg)
+    assert ei.value.status == tk.TK_ENUMERIC
+    mesh.close()
