@@ -40,7 +40,7 @@ template <int N>
 __global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
                                                      int c0, double tol_o, int cap_o, int CS, double* fac_n,
                                                      int* rank_n, const double* Win, double* Wout, double* Wkeep,
-                                                     double rel_thr, double abs_fac) {
+                                                     double rel_thr, double abs_fac, double drop) {
   constexpr int NT = kEigThreads;
   constexpr int LD = N + 1;
   constexpr int NH = N / 2;
@@ -238,13 +238,21 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int
     double tot = 0.0;
     for (int i = 0; i < N; ++i) tot += A[order[i] * LD + order[i]];
     const double thr = tol * tol * tot / 3.0;
-    // smallest r >= 1 with sum_{k >= r} lambda_k <= thr
     int r = N;
-    double tail = 0.0;
-    for (int k = N - 1; k >= 1; --k) {
-      tail += A[order[k] * LD + order[k]];
-      if (tail <= thr) r = k;
-      else break;
+    if (drop > 0.0) {
+      // keep singular values above drop * sigma_1 (eigenvalues above drop^2 lambda_1)
+      const double l0 = A[order[0] * LD + order[0]];
+      r = 0;
+      for (int k = 0; k < N; ++k)
+        if (A[order[k] * LD + order[k]] > drop * drop * l0) ++r;
+    } else {
+      // smallest r >= 1 with sum_{k >= r} lambda_k <= thr
+      double tail = 0.0;
+      for (int k = N - 1; k >= 1; --k) {
+        tail += A[order[k] * LD + order[k]];
+        if (tail <= thr) r = k;
+        else break;
+      }
     }
     if (r > cap) r = cap;
     if (r < 1) r = 1;
@@ -290,6 +298,16 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int
   }
 }
 
+__global__ void k_absxi(int N, const double* nrm, double xi_min, double dxi, double* X) {
+  const int f = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * N * N) return;
+  const int i1 = e % N, i2 = (e / N) % N, i3 = e / (N * N);
+  const double* n = nrm + 3 * (size_t)f;
+  X[(size_t)f * N * N * N + e] =
+      fabs(n[0] * (xi_min + i1 * dxi) + n[1] * (xi_min + i2 * dxi) + n[2] * (xi_min + i3 * dxi));
+}
+
 __global__ void k_identity_basis(int N, size_t count, double* W) {
   const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= count * N * N) return;
@@ -302,11 +320,11 @@ __global__ void k_identity_basis(int N, size_t count, double* W) {
 hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
                       double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
                       const double* Win, double* Wout, double* Wkeep, double rel_thr, double abs_fac,
-                      hipStream_t s) {
+                      hipStream_t s, double drop) {
   if (count <= 0) return hipSuccess;
   dim3 grid(3 * count), blk(kEigThreads);
 #define TK_EIG(NN) hipLaunchKernelGGL(k_eig<NN>, grid, blk, 0, s, G, inst, ip, c0, tol_override, cap_override, CS, \
-                                      fac_n, rank_n, Win, Wout, Wkeep, rel_thr, abs_fac)
+                                      fac_n, rank_n, Win, Wout, Wkeep, rel_thr, abs_fac, drop)
   switch (N) {
     case 16: TK_EIG(16); break;
     case 24: TK_EIG(24); break;
@@ -325,4 +343,14 @@ hipError_t launch_identity_basis(int N, size_t count, double* W, hipStream_t s) 
   return hipGetLastError();
 }
 
+}  // namespace tk
+
+namespace tk {
+hipError_t launch_absxi(int N, int count, const double* normals, double xi_min, double dxi, double* X,
+                        hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int ne = N * N * N;
+  hipLaunchKernelGGL(k_absxi, dim3((ne + 255) / 256, count), dim3(256), 0, s, N, normals, xi_min, dxi, X);
+  return hipGetLastError();
+}
 }  // namespace tk

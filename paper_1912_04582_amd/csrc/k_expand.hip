@@ -410,6 +410,273 @@ __global__ __launch_bounds__(BLOCK) void k_expand_pf(DevState d, int c0, T* X) {
     for (int i = 0; i < N; ++i) out[(size_t)pf[f] * N + i] = acc[f][i];
 }
 
+// ---------------------------------------------------------------------------
+// Meshes with faces off the coordinate axes.  There P_out and P_in of such a
+// face depend on all three velocity indices (xi_n = n.xi is rank 2 by
+// Lemma 1, the |xi_n| estimate has mode ranks <= 6), so the flux weights are
+// evaluated per grid node:
+//   f* = W o f + dt nu f_S + sum_l B_l o g_l,
+//   W   = 1 - dt nu + sum_l a_l (xi_n,l + est_l),   B_l = a_l (xi_n,l - est_l),
+//   a_l = -dt A_l / (2 V)
+// (axis-aligned faces keep their separable form).  Each thread holds one
+// mode-1 fibre per pass in three register arrays: the accumulator, a weight
+// (W or B_l, from the estimate's expansion) and the far side's expansion.
+
+template <int N, int BLOCK, typename T>
+__device__ inline void expand_pass(T (&acc)[N], const T* sU, const T* sG, T* sY, T* sZ, int r1, int r2, int r3,
+                                   int CSL, int pbase) {
+  const T* U1 = sU;
+  const T* U2 = sU + CSL * N;
+  const T* U3 = sU + 2 * CSL * N;
+  const int tid = threadIdx.x;
+  for (int kb = 0; kb < r1; kb += KC) {
+    const int kc = min(KC, r1 - kb);
+    for (int o = tid; o < kc * r2 * N; o += BLOCK) {
+      const int i3 = o % N, t = o / N, k2 = t % r2, j = t / r2;
+      T s = 0;
+      const T* g = sG + (kb + j) + r1 * k2;
+      for (int k3 = 0; k3 < r3; ++k3) s += g[r1 * r2 * k3] * U3[k3 * N + i3];
+      sY[(j * r2 + k2) * N + i3] = s;
+    }
+    __syncthreads();
+    for (int o = tid; o < kc * BLOCK; o += BLOCK) {
+      const int j = o / BLOCK, q = o % BLOCK, pp = pbase + q;
+      const int i2 = pp % N, i3 = pp / N;
+      T s = 0;
+      const T* y = sY + j * r2 * N + i3;
+      for (int k2 = 0; k2 < r2; ++k2) s += U2[k2 * N + i2] * y[k2 * N];
+      sZ[o] = s;
+    }
+    __syncthreads();
+    for (int j = 0; j < kc; ++j) {
+      const T z = sZ[j * BLOCK + tid];
+      const T* u = U1 + (kb + j) * N;
+#pragma unroll
+      for (int i1 = 0; i1 < N; ++i1) acc[i1] += u[i1] * z;
+    }
+    __syncthreads();
+  }
+}
+
+// Stage a Tucker tensor stored with factor stride CSsrc into the LDS layout
+// with stride CSL (rows of mode rev reversed, mode `ax` scaled by
+// coef * max(-sg xi, 0) when coef != 0, core scaled by gsc).
+template <int N, int BLOCK, typename T>
+__device__ inline void stage_any(const double* core, const double* fac, int CSsrc, size_t id, const int (&rr)[3],
+                                 int rev, int ax, double coef, double sg, double xi_min, double dxi, double gsc,
+                                 int CSL, T* sU, T* sG) {
+  const int tid = threadIdx.x;
+  for (int o = tid; o < 3 * CSL * N; o += BLOCK) {
+    const int a = o / (CSL * N), rem = o % (CSL * N), k = rem / N, i = rem % N;
+    if (k >= rr[a]) continue;
+    const int is = (a == rev) ? (N - 1 - i) : i;
+    double v = fac[(id * 3 + a) * CSsrc * N + (size_t)k * N + is];
+    if (a == ax && coef != 0.0) v *= coef * fmax(-sg * (xi_min + i * dxi), 0.0);
+    sU[o] = (T)v;
+  }
+  for (int o = tid; o < rr[0] * rr[1] * rr[2]; o += BLOCK) {
+    const int k1 = o % rr[0], t = o / rr[0], k2 = t % rr[1], k3 = t / rr[1];
+    sG[o] = (T)(core[id * CSsrc * CSsrc * CSsrc + k1 + CSsrc * (k2 + CSsrc * k3)] * gsc);
+  }
+}
+
+template <int N, int BLOCK, typename T>
+__global__ __launch_bounds__(BLOCK) void k_expand_obl(DevState d, int c0, T* X) {
+  constexpr int NPASS = N * N / BLOCK;
+  static_assert(NPASS * BLOCK == N * N, "passes must tile the fibres");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int CS = d.CS;
+  const int CSL = CS > kEstCap ? CS : kEstCap;
+  T* sxi = smem;                  // N
+  T* sd = sxi + N;                // 3 N   separable (axis-aligned) outflow tables
+  T* sU = sd + 3 * N;             // 3 CSL N
+  T* sG = sU + 3 * CSL * N;       // CSL^3
+  T* sY = sG + CSL * CSL * CSL;   // KC CSL N
+  T* sZ = sY + KC * CSL * N;      // KC BLOCK
+  __shared__ double s_nrm[kSlots][3];
+  const int c = c0 + blockIdx.x;
+  const int tid = threadIdx.x;
+  const InstParams P = d.ip[d.inst[c]];
+  const double nu = d.nu[c];
+  if (tid < kSlots * 3) s_nrm[tid / 3][tid % 3] = d.slot_nrm[(size_t)kSlots * 3 * c + tid];
+  for (int i = tid; i < N; i += BLOCK) {
+    const double x = P.xi_min + i * P.dxi;
+    sxi[i] = (T)x;
+    for (int a = 0; a < 3; ++a) {
+      double sum = 0.0;
+      for (int l = 0; l < kSlots; ++l) {
+        const int8_t kind = d.slot_kind[kSlots * c + l];
+        if (kind == SK_NONE || d.slot_axis[kSlots * c + l] != a) continue;
+        sum -= d.slot_coef[kSlots * c + l] * fmax((double)d.slot_sig[kSlots * c + l] * x, 0.0);
+      }
+      sd[a * N + i] = (T)sum;
+    }
+  }
+  __syncthreads();
+  const double* M = d.macro + 8 * (size_t)c;
+  for (int pass = 0; pass < NPASS; ++pass) {
+    const int pbase = pass * BLOCK;
+    const int p = pbase + tid;
+    const int i2 = p % N, i3 = p / N;
+    T acc[N], w[N], tmp[N];
+    // ---- own-cell weight W
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] = 0;
+    for (int l = 0; l < kSlots; ++l) {
+      const int8_t kind = d.slot_kind[kSlots * c + l];
+      if (kind == SK_NONE || d.slot_axis[kSlots * c + l] >= 0) continue;
+      const int e = d.slot_est[kSlots * c + l];
+      const int rr[3] = {d.est_rank[3 * e], d.est_rank[3 * e + 1], d.est_rank[3 * e + 2]};
+      const double al = -0.5 * d.slot_coef[kSlots * c + l];
+      stage_any<N, BLOCK, T>(d.est_core, d.est_fac, kEstCap, (size_t)e, rr, -1, -1, 0.0, 0.0, P.xi_min, P.dxi, al,
+                             CSL, sU, sG);
+      __syncthreads();
+      expand_pass<N, BLOCK, T>(w, sU, sG, sY, sZ, rr[0], rr[1], rr[2], CSL, pbase);
+    }
+    {
+      const T base = (T)(1.0 - P.dt * nu) + sd[N + i2] + sd[2 * N + i3];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double xn = 0.0;
+        for (int l = 0; l < kSlots; ++l) {
+          const int8_t kind = d.slot_kind[kSlots * c + l];
+          if (kind == SK_NONE || d.slot_axis[kSlots * c + l] >= 0) continue;
+          const double al = -0.5 * d.slot_coef[kSlots * c + l];
+          xn += al * (s_nrm[l][0] * (double)sxi[i] + s_nrm[l][1] * (double)sxi[i2] + s_nrm[l][2] * (double)sxi[i3]);
+        }
+        w[i] += base + sd[i] + (T)xn;
+      }
+    }
+    // ---- the cell itself, times W
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = 0;
+    {
+      const int rr[3] = {d.rank[3 * c], d.rank[3 * c + 1], d.rank[3 * c + 2]};
+      stage_any<N, BLOCK, T>(d.core, d.fac, CS, (size_t)c, rr, -1, -1, 0.0, 0.0, P.xi_min, P.dxi, 1.0, CSL, sU, sG);
+      __syncthreads();
+      expand_pass<N, BLOCK, T>(acc, sU, sG, sY, sZ, rr[0], rr[1], rr[2], CSL, pbase);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] *= w[i];
+    // ---- f_S, scaled by dt nu
+    {
+      const double n = M[0], T0 = M[4];
+      const double RT = P.Rg * T0;
+      const double amp = cbrt(n) / sqrt(2.0 * M_PI * RT);
+      const double beta = 1.0 / (2.0 * RT);
+      const double As = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * n * RT * RT);
+      for (int o = tid; o < 3 * N; o += BLOCK) {
+        const int a = o / N, i = o % N;
+        const double v = P.xi_min + i * P.dxi - M[1 + a];
+        const double bse = amp * exp(-v * v * beta);
+        sU[a * CSL * N + 0 * N + i] = (T)bse;
+        sU[a * CSL * N + 1 * N + i] = (T)(bse * v);
+        sU[a * CSL * N + 2 * N + i] = (T)(bse * v * v);
+        sU[a * CSL * N + 3 * N + i] = (T)(bse * v * v * v);
+      }
+      for (int o = tid; o < 64; o += BLOCK) {
+        const int k[3] = {o & 3, (o >> 2) & 3, o >> 4};
+        double g = 0.0;
+        int nz = 0, which = -1;
+        for (int a = 0; a < 3; ++a)
+          if (k[a]) { ++nz; which = a; }
+        if (nz == 0) {
+          g = 1.0;
+        } else if (nz == 1) {
+          if (k[which] == 1) g = -2.5 * As * M[5 + which];
+          else if (k[which] == 3) g = As * beta * M[5 + which];
+        } else if (nz == 2) {
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+              if (a != b && k[a] == 1 && k[b] == 2 && k[3 - a - b] == 0) g = As * beta * M[5 + a];
+        }
+        sG[o] = (T)(P.dt * nu * g);
+      }
+      __syncthreads();
+      expand_pass<N, BLOCK, T>(acc, sU, sG, sY, sZ, 4, 4, 4, CSL, pbase);
+    }
+    // ---- far sides
+    for (int l = 0; l < kSlots; ++l) {
+      const int8_t kind = d.slot_kind[kSlots * c + l];
+      if (kind == SK_NONE) continue;
+      const int ax = d.slot_axis[kSlots * c + l];
+      const double sg = (double)d.slot_sig[kSlots * c + l];
+      const double coef = d.slot_coef[kSlots * c + l];
+      const int nb = d.slot_nb[kSlots * c + l];
+      const bool obl = ax < 0;
+      if (obl) {
+        // B_l = a_l (xi_n - est_l) into w
+        const int e = d.slot_est[kSlots * c + l];
+        const int rr[3] = {d.est_rank[3 * e], d.est_rank[3 * e + 1], d.est_rank[3 * e + 2]};
+        const double al = -0.5 * coef;
+#pragma unroll
+        for (int i = 0; i < N; ++i) w[i] = 0;
+        stage_any<N, BLOCK, T>(d.est_core, d.est_fac, kEstCap, (size_t)e, rr, -1, -1, 0.0, 0.0, P.xi_min, P.dxi, -al,
+                               CSL, sU, sG);
+        __syncthreads();
+        expand_pass<N, BLOCK, T>(w, sU, sG, sY, sZ, rr[0], rr[1], rr[2], CSL, pbase);
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+          w[i] += (T)(al * (s_nrm[l][0] * (double)sxi[i] + s_nrm[l][1] * (double)sxi[i2] +
+                            s_nrm[l][2] * (double)sxi[i3]));
+#pragma unroll
+        for (int i = 0; i < N; ++i) tmp[i] = 0;
+      }
+      // the far side, row-scaled on axis-aligned faces, plain on oblique ones
+      const double rc = obl ? 0.0 : coef;
+      if (kind == SK_INTERIOR || kind == SK_OUTFLOW || kind == SK_SYM) {
+        const int src = (kind == SK_INTERIOR) ? nb : c;
+        const int rr[3] = {d.rank[3 * src], d.rank[3 * src + 1], d.rank[3 * src + 2]};
+        stage_any<N, BLOCK, T>(d.core, d.fac, CS, (size_t)src, rr, kind == SK_SYM ? ax : -1, ax, rc, sg, P.xi_min,
+                               P.dxi, 1.0, CSL, sU, sG);
+        __syncthreads();
+        if (obl) expand_pass<N, BLOCK, T>(tmp, sU, sG, sY, sZ, rr[0], rr[1], rr[2], CSL, pbase);
+        else expand_pass<N, BLOCK, T>(acc, sU, sG, sY, sZ, rr[0], rr[1], rr[2], CSL, pbase);
+      } else {
+        const double gsc = (kind == SK_WALL) ? d.nw[kSlots * c + l] : 1.0;
+        const double* bf = d.bc_fac + (size_t)nb * 3 * N;
+        for (int o = tid; o < 3 * N; o += BLOCK) {
+          const int a = o / N, i = o % N;
+          double v = bf[o];
+          if (a == ax && !obl) v *= coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0);
+          sU[a * CSL * N + i] = (T)v;
+        }
+        if (tid == 0) sG[0] = (T)gsc;
+        __syncthreads();
+        if (obl) expand_pass<N, BLOCK, T>(tmp, sU, sG, sY, sZ, 1, 1, 1, CSL, pbase);
+        else expand_pass<N, BLOCK, T>(acc, sU, sG, sY, sZ, 1, 1, 1, CSL, pbase);
+      }
+      if (obl) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] += tmp[i] * w[i];
+      }
+    }
+    T* out = X + (size_t)blockIdx.x * N * N * N + (size_t)p * N;
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = acc[i];
+  }
+}
+
+template <int N>
+struct OblShape;
+template <> struct OblShape<16> { static constexpr int B = 256; };
+template <> struct OblShape<24> { static constexpr int B = 288; };
+template <> struct OblShape<32> { static constexpr int B = 512; };
+template <> struct OblShape<48> { static constexpr int B = 384; };
+
+template <int N, typename T>
+hipError_t launch_expand_obl_t(const DevState& d, int c0, int count, void* X, hipStream_t s) {
+  constexpr int B = OblShape<N>::B;
+  const int CSL = d.CS > kEstCap ? d.CS : kEstCap;
+  const size_t sh = sizeof(T) * (4 * N + 3 * CSL * N + CSL * CSL * CSL + KC * CSL * N + KC * B);
+  auto k = k_expand_obl<N, B, T>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(count), dim3(B), sh, s, d, c0, (T*)X);
+  return hipGetLastError();
+}
+
 // Plain expansion of state-layout Tucker tensors (rounding test hook).
 template <int N, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_expand_plain(int CS, const double* core, const double* fac,
@@ -467,8 +734,25 @@ hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, hipStr
 
 }  // namespace
 
-hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixed, hipStream_t s) {
+hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixed, int oblique, hipStream_t s) {
   if (count <= 0) return hipSuccess;
+  if (oblique) {
+    if (mixed) {
+      switch (d.N) {
+        case 16: return launch_expand_obl_t<16, float>(d, c0, count, X, s);
+        case 24: return launch_expand_obl_t<24, float>(d, c0, count, X, s);
+        case 32: return launch_expand_obl_t<32, float>(d, c0, count, X, s);
+        case 48: return launch_expand_obl_t<48, float>(d, c0, count, X, s);
+      }
+    } else {
+      switch (d.N) {
+        case 16: return launch_expand_obl_t<16, double>(d, c0, count, X, s);
+        case 24: return launch_expand_obl_t<24, double>(d, c0, count, X, s);
+        case 32: return launch_expand_obl_t<32, double>(d, c0, count, X, s);
+      }
+    }
+    return hipErrorInvalidValue;
+  }
   if (mixed) {
     switch (d.N) {
       case 16: return launch_expand_t<16, float>(d, c0, count, X, s);

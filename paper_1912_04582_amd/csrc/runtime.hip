@@ -131,21 +131,33 @@ static tk_status mesh_build(tk_ctx* ctx, const tk_mesh_desc* d, tk_mesh* m) {
   m->slot_sig.assign((size_t)nc * kSlots, 1);
   m->slot_area.assign((size_t)nc * kSlots, 0.0);
   m->slot_l1.assign((size_t)nc * kSlots, 0.0);
+  m->slot_nrm.assign((size_t)nc * kSlots * 3, 0.0);
+  m->slot_face.assign((size_t)nc * kSlots, -1);
+  m->face_normal.assign(d->face_normal, d->face_normal + 3 * (size_t)nf);
+  m->oblique = false;
   std::vector<int> cnt(nc, 0);
+  int cur_face = -1;
   std::vector<double> close((size_t)nc * 3, 0.0), asum(nc, 0.0);
   auto add_slot = [&](int c, int nb, int8_t kind, const double* e, double sgn, double A) -> tk_status {
     if (cnt[c] >= kSlots) return ctx_fail(ctx, TK_EINVAL, "mesh: cell " + std::to_string(c) + " has more than 6 faces");
     int axis = -1, nz = 0;
     for (int a = 0; a < 3; ++a)
       if (e[a] != 0.0) { axis = a; ++nz; }
-    if (nz != 1 || std::fabs(std::fabs(e[axis]) - 1.0) > 1e-12)
-      return ctx_fail(ctx, TK_EINVAL, "mesh: face normals off the coordinate axes are not supported");
+    const bool on_axis = (nz == 1 && std::fabs(std::fabs(e[axis]) - 1.0) <= 1e-12);
+    if (!on_axis) {
+      axis = -1;
+      if (kind == SK_SYM || kind == SK_WALL)
+        return ctx_fail(ctx, TK_EINVAL, "mesh: symmetry and wall faces must lie on coordinate-axis planes");
+      m->oblique = true;
+    }
     const int s = cnt[c]++;
     const size_t k = (size_t)c * kSlots + s;
     m->slot_nb[k] = nb;
     m->slot_kind[k] = kind;
     m->slot_axis[k] = (int8_t)axis;
-    m->slot_sig[k] = (int8_t)((sgn * e[axis]) > 0 ? 1 : -1);
+    m->slot_sig[k] = (int8_t)((on_axis ? sgn * e[axis] : sgn) > 0 ? 1 : -1);
+    for (int a = 0; a < 3; ++a) m->slot_nrm[3 * k + a] = sgn * e[a];
+    m->slot_face[k] = cur_face;
     m->slot_area[k] = A;
     m->slot_l1[k] = A * (std::fabs(e[0]) + std::fabs(e[1]) + std::fabs(e[2]));
     for (int a = 0; a < 3; ++a) close[3 * c + a] += sgn * A * e[a];
@@ -153,6 +165,7 @@ static tk_status mesh_build(tk_ctx* ctx, const tk_mesh_desc* d, tk_mesh* m) {
     return TK_OK;
   };
   for (int j = 0; j < nf; ++j) {
+    cur_face = j;
     const int L = d->face_left[j], R = d->face_right[j];
     const double* e = d->face_normal + 3 * (size_t)j;
     const double A = d->face_area[j];
@@ -246,6 +259,11 @@ DevState state_dev(const tk_state* st) {
   d.nu = st->d_nu;
   d.nw = st->d_nw;
   d.flag = st->d_flag;
+  d.slot_nrm = st->d_slot_nrm;
+  d.slot_est = st->d_slot_est;
+  d.est_core = st->d_est_core;
+  d.est_fac = st->d_est_fac;
+  d.est_rank = st->d_est_rank;
   return d;
 }
 
@@ -317,6 +335,13 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
   std::vector<double> slot_coef((size_t)nc * kSlots), vol(nc), bc_fac((size_t)std::max(nbc, 1) * 3 * N, 0.0);
   std::vector<double> macro5((size_t)nc * 5);
   std::vector<InstParams> ip(count);
+  std::vector<double> slot_nrm((size_t)nc * kSlots * 3, 0.0);
+  std::vector<int> slot_est((size_t)nc * kSlots, -1);
+  std::vector<double> est_nrm;   // normals of the oblique faces
+  std::vector<int> est_inst;     // owning instance of each estimate
+  bool oblique = false;
+  for (int k = 0; k < count; ++k) oblique |= meshes[k]->oblique;
+  if (oblique && plain) return ctx_fail(ctx, TK_EINVAL, "plain comparator: faces off the coordinate axes are not supported");
   st->inst_off.assign(count + 1, 0);
   int c0 = 0, b0 = 0;
   for (int k = 0; k < count; ++k) {
@@ -348,6 +373,7 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     P.tol = p.tol;
     P.cap = p.rank_cap;
     P.pad = 0;
+    std::vector<int> face_est(m->oblique ? m->n_faces : 0, -1);
     for (int c = 0; c < m->n_cells; ++c) {
       const int g = c0 + c;
       inst[g] = k;
@@ -361,6 +387,16 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
         slot_sig[dst] = m->slot_sig[src];
         slot_coef[dst] = dt * m->slot_area[src] / m->volume[c];
         slot_nb[dst] = (kind == SK_INTERIOR) ? m->slot_nb[src] + c0 : (kind == SK_NONE ? -1 : m->slot_nb[src] + b0);
+        for (int a = 0; a < 3; ++a) slot_nrm[3 * dst + a] = m->slot_nrm[3 * src + a];
+        if (kind != SK_NONE && m->slot_axis[src] < 0) {
+          const int j = m->slot_face[src];
+          if (face_est[j] < 0) {
+            face_est[j] = (int)est_inst.size();
+            est_inst.push_back(k);
+            for (int a = 0; a < 3; ++a) est_nrm.push_back(m->face_normal[3 * (size_t)j + a]);
+          }
+          slot_est[dst] = face_est[j];
+        }
       }
     }
     // rank-1 boundary Maxwellian factors
@@ -419,6 +455,16 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
   ALLOC(d_flag, int, 1);
   ALLOC(d_resid, double, count);
   ALLOC(d_macro5, double, (size_t)nc * 5);
+  const int n_est = (int)est_inst.size();
+  S->oblique = oblique;
+  S->n_est = n_est;
+  if (oblique) {
+    ALLOC(d_slot_nrm, double, (size_t)nc * kSlots * 3);
+    ALLOC(d_slot_est, int, (size_t)nc * kSlots);
+    ALLOC(d_est_core, double, (size_t)std::max(n_est, 1) * kEstCap * kEstCap * kEstCap);
+    ALLOC(d_est_fac, double, (size_t)std::max(n_est, 1) * 3 * kEstCap * N);
+    ALLOC(d_est_rank, int, (size_t)std::max(n_est, 1) * 3);
+  }
   if (plain) {
     for (int b = 0; b < 2; ++b) {
       S->pf[b] = st_alloc(S, tsz * (size_t)nc * N * N * N, &s);
@@ -453,6 +499,10 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
   up(S->d_vol, vol.data(), sizeof(double) * nc);
   up(S->d_inst_off, st->inst_off.data(), sizeof(int) * (count + 1));
   up(S->d_macro5, macro5.data(), sizeof(double) * macro5.size());
+  if (oblique) {
+    up(S->d_slot_nrm, slot_nrm.data(), sizeof(double) * slot_nrm.size());
+    up(S->d_slot_est, slot_est.data(), sizeof(int) * slot_est.size());
+  }
   if (e == hipSuccess) e = hipMemsetAsync(S->d_flag, 0, sizeof(int), q);
   if (e == hipSuccess) e = hipMemsetAsync(S->d_nw, 0, sizeof(double) * (size_t)nc * kSlots, q);
   if (e == hipSuccess) e = hipMemsetAsync(S->d_macro, 0, sizeof(double) * (size_t)nc * 8, q);
@@ -469,6 +519,40 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     }
     if (e == hipSuccess) e = launch_init_maxwell(state_dev(S), S->d_macro5, q);
     if (e == hipSuccess) e = launch_identity_basis(N, (size_t)nc * 3, S->Wkeep, q);
+    if (e == hipSuccess && oblique && n_est > 0) {
+      // |xi . e| estimate of every oblique face: truncated HOSVD of the exact
+      // tensor, mode ranks <= kEstCap, singular values <= kEstDrop sigma_1 dropped
+      const int fch = 2048;
+      tk_status s2 = TK_OK;
+      double* d_nrm = (double*)ctx_alloc(ctx, sizeof(double) * 3 * n_est, &s2);
+      double* d_X = d_nrm ? (double*)ctx_alloc(ctx, sizeof(double) * (size_t)fch * N * N * N, &s2) : nullptr;
+      double* d_Gm = d_X ? (double*)ctx_alloc(ctx, sizeof(double) * (size_t)fch * 3 * N * N, &s2) : nullptr;
+      if (!d_Gm) {
+        ctx_free(ctx, d_nrm); ctx_free(ctx, d_X);
+        state_free(S);
+        return s2;
+      }
+      e = hipMemcpyAsync(d_nrm, est_nrm.data(), sizeof(double) * est_nrm.size(), hipMemcpyHostToDevice, q);
+      int f0 = 0;
+      while (f0 < n_est && e == hipSuccess) {
+        const int cnt = std::min(fch, n_est - f0);
+        // every instance of a state shares N; the velocity grid is per instance:
+        // one launch covers consecutive faces on the same grid
+        const InstParams& P0 = ip[est_inst[f0]];
+        int cnt2 = 1;
+        while (cnt2 < cnt && ip[est_inst[f0 + cnt2]].dxi == P0.dxi) ++cnt2;
+        e = launch_absxi(N, cnt2, d_nrm + 3 * (size_t)f0, P0.xi_min, P0.dxi, d_X, q);
+        if (e == hipSuccess) e = launch_gram(N, cnt2, d_X, 0, d_Gm, q);
+        if (e == hipSuccess)
+          e = launch_eig(N, cnt2, d_Gm, nullptr, nullptr, f0, 0.0, kEstCap, kEstCap, S->d_est_fac, S->d_est_rank,
+                         nullptr, nullptr, nullptr, 1e-15, 1e-18, q, kEstDrop);
+        if (e == hipSuccess)
+          e = launch_project(N, cnt2, d_X, 0, f0, kEstCap, S->d_est_fac, S->d_est_rank, S->d_est_core, q);
+        f0 += cnt2;
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(q);
+      ctx_free(ctx, d_nrm); ctx_free(ctx, d_X); ctx_free(ctx, d_Gm);
+    }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(q);
   if (e != hipSuccess) { state_free(S); return ctx_hip(ctx, e, "state init"); }
@@ -503,7 +587,7 @@ static tk_status state_step_once(tk_state* st) {
   for (int c0 = 0; c0 < st->nc; c0 += st->chunk) {
     const int cnt = std::min(st->chunk, st->nc - c0);
     prof_begin(ctx, KID_EXPAND, &ev);
-    e = launch_expand(d, c0, cnt, st->X, st->mixed, q);
+    e = launch_expand(d, c0, cnt, st->X, st->mixed, st->oblique ? 1 : 0, q);
     prof_end(ctx, KID_EXPAND, ev);
     if (e != hipSuccess) return ctx_hip(ctx, e, "expand");
     prof_begin(ctx, KID_GRAM, &ev);

@@ -15,6 +15,8 @@ namespace tk {
 
 constexpr int kMaxCap = 16;  // largest Tucker rank per mode
 constexpr int kSlots = 6;    // faces per hexahedral cell
+constexpr int kEstCap = 6;   // mode ranks of the |xi.e| estimate on oblique faces
+constexpr double kEstDrop = 1e-14;  // estimate: drop singular values <= kEstDrop sigma_1
 
 // Kind of the cell on the far side of a face slot.
 enum SlotKind : int8_t {
@@ -62,6 +64,12 @@ struct DevState {
   double* nu;
   double* nw;      // [nc][6]
   int* flag;       // numeric error flag
+  // oblique faces (slot_axis < 0): outward normal, estimate index and data
+  const double* slot_nrm;  // [nc][6][3]
+  const int* slot_est;     // [nc][6]
+  const double* est_core;  // [n_est][kEstCap^3]
+  const double* est_fac;   // [n_est][3][kEstCap][N]
+  const int* est_rank;     // [n_est][3]
 };
 
 // Kernel families (names used by the profiler interface).
@@ -72,7 +80,7 @@ extern const char* kKernelNames[KID_COUNT];
 // ---- launchers (each enqueues on `s`) -------------------------------------
 hipError_t launch_init_maxwell(const DevState& d, const double* macro5, hipStream_t s);
 hipError_t launch_moments(const DevState& d, hipStream_t s);
-hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixed, hipStream_t s);
+hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixed, int oblique, hipStream_t s);
 hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hipStream_t s);
 // eig of Grams [count][3][N][N]; writes factors/ranks of cells c0.. into the
 // next buffers (tol/cap per instance via inst/ip, or the overrides when
@@ -80,7 +88,10 @@ hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hi
 hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
                       double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
                       const double* Win, double* Wout, double* Wkeep, double rel_thr, double abs_fac,
-                      hipStream_t s);
+                      hipStream_t s, double drop = 0.0);
+// |xi . e| on the full grid for `count` unit normals (FP64), for the estimate
+hipError_t launch_absxi(int N, int count, const double* normals, double xi_min, double dxi, double* X,
+                        hipStream_t s);
 // set `count` N x N bases to the identity (cold start of the warm-started eigensolver)
 hipError_t launch_identity_basis(int N, size_t count, double* W, hipStream_t s);
 // Gram of the rotated unfoldings: G2_a = (W_a^T A_(a)) (W_a^T A_(a))^T

@@ -39,6 +39,10 @@ struct tk_mesh {
   std::vector<int8_t> slot_sig;    // outward orientation along the axis
   std::vector<double> slot_area;
   std::vector<double> slot_l1;     // A ||e||_1
+  std::vector<double> slot_nrm;    // [nc][6][3] outward unit normal
+  std::vector<int> slot_face;      // face index of the slot
+  bool oblique = false;            // some face normal is off the coordinate axes
+  std::vector<double> face_normal; // [n_faces][3]
 };
 
 struct tk_state {
@@ -78,6 +82,14 @@ struct tk_state {
   // rounding workspaces
   void* X = nullptr;
   double* G = nullptr;
+  // oblique faces: per-slot outward normal and index of the |xi.e| estimate
+  bool oblique = false;
+  int n_est = 0;
+  double* d_slot_nrm = nullptr;
+  int* d_slot_est = nullptr;
+  double* d_est_core = nullptr;  // [n_est][6^3]
+  double* d_est_fac = nullptr;   // [n_est][3][6][N]
+  int* d_est_rank = nullptr;     // [n_est][3]
   double* Wb = nullptr;     // first-pass bases of the FP64 refinement
   double* Wkeep = nullptr;  // [nc][3][N][N] previous full eigenbases (warm start)
   // plain comparator storage

@@ -73,9 +73,23 @@ def test_bad_indices_rejected():
     _expect_einval(m, "boundary index")
 
 
-def test_oblique_faces_rejected():
-    m = synth.jittered_box(3, 3, 3, 1 / 3, seed=0)
-    _expect_einval(m, "coordinate axes")
+def test_oblique_faces_accepted():
+    ctx = host_ctx()
+    try:
+        tk.Mesh(ctx, synth.jittered_box(3, 3, 3, 1 / 3, seed=0)).close()
+    finally:
+        ctx.close()
+
+
+def test_oblique_symmetry_face_rejected():
+    # one closed cube cell whose x faces are tilted symmetry planes
+    c, s = np.cos(0.3), np.sin(0.3)
+    nrm = np.array([[c, s, 0.0], [-c, -s, 0.0], [0, 1.0, 0], [0, -1.0, 0], [0, 0, 1.0], [0, 0, -1.0]])
+    m = {"n_cells": 1, "n_faces": 6, "face_left": np.zeros(6, dtype=np.int32),
+         "face_right": -np.ones(6, dtype=np.int32), "face_normal": nrm, "face_area": np.ones(6),
+         "cell_volume": np.ones(1), "cell_center": np.zeros((1, 3)),
+         "bc": [{"kind": synth.BC_SYM}]}
+    _expect_einval(m, "coordinate-axis planes")
 
 
 def test_too_many_faces_rejected():

@@ -252,3 +252,30 @@ def test_invalid_arguments_rejected(ctx):
         tk.State(ctx, mesh, cfg, neg)
     assert ei.value.status == tk.TK_ENUMERIC
     mesh.close()
+
+
+def full_macros(S, F):
+    out = []
+    for i in range(S.mesh["n_cells"]):
+        n, u, T, q = kin.macros_full(F[i], S.xi, S.dxi, S.Rg, S.m)
+        out.append([n, *u, T, *q])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("precision,N,cap,tol,steps,bar", [("fp64", 16, 6, 1e-6, 3, 1e-10),
+                                                          ("mixed", 24, 6, 1e-5, 2, 1e-5)])
+def test_jittered_mesh_oblique_faces(ctx, precision, N, cap, tol, steps, bar):
+    """Faces off the coordinate axes: rank-6 |xi.e| estimates and Hadamard flux terms."""
+    m = synth.jittered_box(3, 3, 3, 1 / 3, seed=7)
+    cfg = dict(N=N, xi_max=4.5, cap=cap, tol=tol, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=0.2, Rg=0.5, m=1.0,
+               seed=31, init="random", precision=precision)
+    m0 = synth.initial_macros(cfg, m)
+    mesh, st = gpu_state(ctx, m, cfg, m0)
+    st.step(steps)
+    got = st.moments()
+    S = fv.Setup(m, cfg, m0)
+    F = dvm.run_full(S, m0, steps)
+    err, _ = macro_rel_err(got, full_macros(S, F))
+    print(f"jittered {precision} N={N} {steps} steps max rel macro err {err:.3e}")
+    assert err < bar, err
+    st.close(); mesh.close()
