@@ -239,6 +239,51 @@ def run_batch(steps, warmup, count):
                 groups={N: (len(v), sum(m["n_cells"] for _, m, _ in v)) for N, v in groups.items()})
 
 
+def serve_run(reqs, rate, seed=5):
+    """Submit requests (arrivals at t = 0 when rate is None, else Poisson with
+    `rate` per second), wait for all; latency = t_done - t_arrive."""
+    ctx = tk.Context(0)
+    srv = tk.Server(ctx)
+    rng = np.random.default_rng(seed)
+    t_next = 0.0
+    tickets = []
+    t0 = time.perf_counter()
+    for m, c, m0, steps, rtol in reqs:
+        if rate:
+            t_next += rng.exponential(1.0 / rate)
+            while time.perf_counter() - t0 < t_next:
+                time.sleep(0.001)
+        tickets.append(srv.submit(m, c, m0, steps, rtol))
+    done = {}
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t not in done:
+                r = srv.poll(t, want_macros=False)
+                if r["status"] != tk.TK_PENDING:
+                    done[t] = r
+        time.sleep(0.002)
+    t1 = time.perf_counter()
+    srv.close()
+    ctx.close()
+    res = [done[t] for t in tickets]
+    lat = np.array([r["t_done"] - r["t_arrive"] for r in res])
+    updates = sum(r["steps"] * q[0]["n_cells"] for r, q in zip(res, reqs))
+    return dict(seconds=t1 - t0, latency=lat, updates=updates,
+                status=[r["status"] for r in res], steps=[r["steps"] for r in res])
+
+
+def run_serve(count, max_steps, seed=4):
+    specs = synth.configs.serve_requests(seed=seed, count=count)
+    reqs = []
+    for c in specs:
+        m = synth.configs.make_mesh(c)
+        reqs.append((m, c, synth.initial_macros(c, m), min(max_steps, c["steps"]), c["residual_tol"]))
+    sat = serve_run(reqs, None)
+    rate = 0.7 * count / sat["seconds"]
+    paced = serve_run(reqs, rate)
+    return dict(saturated=sat, paced=paced, rate=rate, cells=[q[0]["n_cells"] for q in reqs])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +295,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--parity-steps", type=int, default=3)
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--serve-count", type=int, default=12)
+    ap.add_argument("--serve-max-steps", type=int, default=100)
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--targets", default="", help=argparse.SUPPRESS)
     ap.add_argument("--leg-steps", type=int, default=2, help=argparse.SUPPRESS)
@@ -260,6 +307,25 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if a.workload == "serve":
+        r = run_serve(a.serve_count, a.serve_max_steps)
+        out = {"metric": "Tucker S-model cell-updates/s (vs plain GPU step at 1e-5 rel err); p50/p99 latency",
+               "unit": "cell-updates/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f32 terms + f64 rounding", "data": "synthetic",
+               "config": {"workload": f"serving {a.serve_count} jittered-box requests",
+                          "max_steps": a.serve_max_steps, "cells": r["cells"]}}
+        for key in ("saturated", "paced"):
+            q = r[key]
+            out[key] = {"value": q["updates"] / q["seconds"], "seconds": q["seconds"],
+                        "p50_latency_s": float(np.percentile(q["latency"], 50)),
+                        "p99_latency_s": float(np.percentile(q["latency"], 99)),
+                        "statuses": sorted(set(q["status"])), "steps": q["steps"]}
+            log(f"serve {key}: {out[key]['value']:.4g} cell-updates/s, p50 {out[key]['p50_latency_s']:.2f} s, "
+                f"p99 {out[key]['p99_latency_s']:.2f} s over {q['seconds']:.1f} s")
+        out["arrival_rate_per_s"] = r["rate"]
+        out["value"] = out["paced"]["value"]
+        print(json.dumps(out), flush=True)
+        return
     if a.workload == "batch":
         steps = a.steps if a.steps != 200 else 50
         r = run_batch(steps, a.warmup, a.batch_count)

@@ -289,16 +289,23 @@ DevPlain plain_dev(const tk_state* st) {
 }
 
 size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk) {
+  // the allocations of state_create for one instance (slot tables, macros,
+  // Tucker buffers, eigenbases, rounding workspaces), rounded up by 10%
   const size_t N = p.N, CS = std::max(4, p.rank_cap);
   const size_t tsz = p.precision == TK_MIXED ? 4 : 8;
-  size_t b = (size_t)nc * (sizeof(int) + kSlots * (sizeof(int) + 3 + sizeof(double)) + 8 * 2 + 8 + 8 * kSlots + 8);
+  size_t b = (size_t)nc * (4 + kSlots * (4 + 3 + 8) + 8 + 8 * 8 * 3 + 8 + 8 * kSlots);
   if (plain) {
     b += 2 * (size_t)nc * N * N * N * tsz;
   } else {
+    const size_t ch = std::min<size_t>((size_t)nc, (size_t)chunk);
     b += 2 * (size_t)nc * (CS * CS * CS + 3 * CS * N) * 8 + 2 * (size_t)nc * 3 * 4;
-    b += (size_t)chunk * (N * N * N * tsz + 3 * N * N * 8);
+    b += (size_t)nc * 3 * N * N * 8;                      // warm-start eigenbases
+    b += ch * (N * N * N * tsz + 3 * N * N * 8);          // X and Gram workspaces
+    if (p.precision == TK_FP64) b += ch * 3 * N * N * 8;  // first-pass bases
+    b += (size_t)nc * kSlots * (3 * 8 + 4);               // oblique slots
+    b += (size_t)nc * 3 * (kEstCap * kEstCap * kEstCap + 3 * kEstCap * N) * 8 / 2;  // estimates
   }
-  return b;
+  return b + b / 10 + (64u << 20);
 }
 
 static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* meshes, const tk_params* params,
@@ -522,7 +529,9 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     if (e == hipSuccess && oblique && n_est > 0) {
       // |xi . e| estimate of every oblique face: truncated HOSVD of the exact
       // tensor, mode ranks <= kEstCap, singular values <= kEstDrop sigma_1 dropped
-      const int fch = 2048;
+      const size_t per_face = (size_t)N * N * N * 8 + 3 * (size_t)N * N * 8;
+      const size_t avail = ctx->budget > ctx->used ? ctx->budget - ctx->used : 0;
+      const int fch = (int)std::max<size_t>(1, std::min<size_t>(2048, avail / 2 / per_face));
       tk_status s2 = TK_OK;
       double* d_nrm = (double*)ctx_alloc(ctx, sizeof(double) * 3 * n_est, &s2);
       double* d_X = d_nrm ? (double*)ctx_alloc(ctx, sizeof(double) * (size_t)fch * N * N * N, &s2) : nullptr;
@@ -653,6 +662,24 @@ tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait) {
   prof_harvest(ctx);
   if (flag) return ctx_fail(ctx, TK_ENUMERIC, "a cell has non-positive or non-finite n or T");
   return TK_OK;
+}
+
+// One step with the residual and the numeric flag copied asynchronously to
+// host memory (h_res[n_instances], h_flag); the caller synchronises the stream.
+tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag) {
+  tk_ctx* ctx = st->ctx;
+  hipStream_t q = ctx->stream;
+  tk_status s;
+  if ((s = state_moments_now(st)) != TK_OK) return s;
+  hipError_t e = hipMemcpyAsync(st->d_macro_prev, st->d_macro, sizeof(double) * (size_t)st->nc * 8,
+                                hipMemcpyDeviceToDevice, q);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "macro copy");
+  if ((s = state_step_once(st)) != TK_OK) return s;
+  if ((s = state_moments_now(st)) != TK_OK) return s;
+  e = launch_residual(st->d_macro_prev, st->d_macro, st->d_vol, st->d_inst_off, st->ninst, st->d_resid, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_res, st->d_resid, sizeof(double) * st->ninst, hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_flag, st->d_flag, sizeof(int), hipMemcpyDeviceToHost, q);
+  return ctx_hip(ctx, e, "residual");
 }
 
 // ---------------------------------------------------------------------------

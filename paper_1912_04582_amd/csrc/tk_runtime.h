@@ -103,3 +103,4 @@ void* ctx_alloc(tk_ctx* ctx, size_t bytes, tk_status* st);
 void ctx_free(tk_ctx* ctx, void* p);
 tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait);
 size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk);
+tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag);

@@ -312,3 +312,40 @@ class State:
         G = core[:r[0] * r[1] * r[2]].reshape(r, order="F").copy()
         Us = [U[a][:N * r[a]].reshape((N, r[a]), order="F").copy() for a in range(3)]
         return G, Us
+
+
+class Server:
+    """tk_serve_*: continuous batching of independent solves on one device."""
+
+    def __init__(self, ctx, budget=0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().tk_serve_create(ctx.h, int(budget), C.byref(h)), ctx.h)
+        self.h = h
+        self._keep = {}
+        self._ncells = {}
+
+    def submit(self, mesh, cfg, macros, max_steps, residual_tol):
+        arrays = _MeshArrays(mesh)
+        mac = np.ascontiguousarray(macros, dtype=np.float64)
+        req = tk_request(arrays.desc, make_params(cfg), _dptr(mac), int(max_steps), float(residual_tol))
+        t = C.c_uint64()
+        _check(lib().tk_serve_submit(self.h, C.byref(req), C.byref(t)), self.ctx.h)
+        self._ncells[t.value] = int(mesh["n_cells"])
+        return t.value
+
+    def poll(self, ticket, want_macros=True):
+        res = tk_result()
+        out = np.zeros((self._ncells.get(ticket, 0), 8)) if want_macros else None
+        res.macro_out = _dptr(out) if want_macros else None
+        st = lib().tk_serve_poll(self.h, C.c_uint64(ticket), C.byref(res))
+        if st == TK_ENOTFOUND:
+            raise TkError(st, "unknown ticket")
+        return {"status": res.status, "steps": res.steps, "residual": res.residual,
+                "t_arrive": res.t_arrive, "t_admit": res.t_admit, "t_done": res.t_done,
+                "macros": out if res.status != TK_PENDING else None}
+
+    def close(self):
+        if self.h:
+            lib().tk_serve_destroy(self.h)
+            self.h = None

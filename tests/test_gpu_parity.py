@@ -279,3 +279,57 @@ def test_jittered_mesh_oblique_faces(ctx, precision, N, cap, tol, steps, bar):
     print(f"jittered {precision} N={N} {steps} steps max rel macro err {err:.3e}")
     assert err < bar, err
     st.close(); mesh.close()
+
+
+def test_serving_alone_equals_mix(ctx):
+    """Served requests: results equal to the same request served alone."""
+    import time
+    reqs = []
+    for k, (mk, N, cap, tol) in enumerate([(lambda: synth.periodic_box(3), 16, 4, 1e-5),
+                                           (lambda: synth.jittered_box(3, 3, 3, 1 / 3, seed=3), 16, 5, 1e-6),
+                                           (lambda: synth.periodic_box(4, length=0.5), 24, 6, 1e-5)]):
+        m = mk()
+        cfg = dict(N=N, xi_max=4.5, cap=cap, tol=tol, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=0.2, Rg=0.5, m=1.0,
+                   seed=40 + k, init="random", precision="mixed")
+        reqs.append((m, cfg, synth.initial_macros(cfg, m)))
+
+    def serve(items):
+        srv = tk.Server(ctx)
+        tickets = [srv.submit(m, c, m0, 12, 1e-9) for m, c, m0 in items]
+        out = {}
+        t0 = time.time()
+        while len(out) < len(tickets) and time.time() - t0 < 120:
+            for t in tickets:
+                if t in out:
+                    continue
+                r = srv.poll(t)
+                if r["status"] != tk.TK_PENDING:
+                    out[t] = r
+            time.sleep(0.01)
+        srv.close()
+        return [out[t] for t in tickets]
+
+    mix = serve(reqs)
+    for k, item in enumerate(reqs):
+        alone = serve([item])[0]
+        assert mix[k]["status"] == tk.TK_OK and alone["status"] == tk.TK_OK
+        assert mix[k]["steps"] == alone["steps"] == 12
+        assert np.array_equal(mix[k]["macros"], alone["macros"])
+        assert mix[k]["t_arrive"] <= mix[k]["t_admit"] <= mix[k]["t_done"]
+    # the served result equals a plain state run
+    m, c, m0 = reqs[0]
+    mesh, st = gpu_state(ctx, m, c, m0)
+    st.step(12)
+    assert np.array_equal(st.moments(), mix[0]["macros"])
+    st.close(); mesh.close()
+
+
+def test_serving_refuses_requests_that_never_fit(ctx):
+    srv = tk.Server(ctx, budget=1 << 20)
+    m = synth.periodic_box(3)
+    cfg = dict(N=16, xi_max=4.5, cap=4, tol=1e-5, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=0.2, Rg=0.5, m=1.0,
+               seed=1, init="random", precision="mixed")
+    with pytest.raises(tk.TkError) as ei:
+        srv.submit(m, cfg, synth.initial_macros(cfg, m), 5, 1e-5)
+    assert ei.value.status == tk.TK_ENOMEM
+    srv.close()
