@@ -183,6 +183,7 @@ def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True):
         ctx.sync()
         ctx.prof_reset()
         ctx.prof_enable(prof)
+        ctx.eig_stats(reset=True)
         r0 = None if plain else st.ranks()[0]
         t0 = time.perf_counter()
         st.step(steps)  # waits for completion
@@ -190,6 +191,9 @@ def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True):
         ctx.prof_enable(False)
         fams = ["moments", "expand", "gram", "eig", "project"] if not plain else ["plain_moments", "plain_step"]
         prof_ms = {f: ctx.prof_get(f) for f in fams}
+        eig = ctx.eig_stats(reset=True)
+        if not plain:
+            log(f"  eigensolver: {eig}")
         r1, C = (None, None) if plain else st.ranks()
         st.close()
         tm.close()

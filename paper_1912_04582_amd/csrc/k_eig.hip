@@ -15,7 +15,13 @@
 // Warm start: a cell's Gram changes little from one time step to the next,
 // so the full eigenbasis of the previous step is kept per cell and mode
 // (`Wkeep`); the matrix is first rotated into it (A = W^T G W, V = W) and
-// Jacobi then only removes the small off-diagonal remainder.  Rounds in
+// Jacobi then only removes the small off-diagonal remainder.  With `lead`
+// > 0 only the leading k = r_prev + lead vectors of that basis are used when
+// the rest of the spectrum carries at most 1e-3 of the truncation budget
+// eps^2 trace / 3 (its share then enters the discarded sum); the k x k
+// block W_k^T G W_k is diagonalised and the remaining basis vectors are kept.
+// A rank that comes within 2 of k, or a larger remainder, falls back to the
+// full matrix.  Rounds in
 // which no pair needs a rotation skip the update passes; convergence is
 // checked by a parallel scan of the off-diagonal elements before each sweep.
 //
@@ -36,101 +42,60 @@ namespace {
 
 constexpr int kEigThreads = 256;
 
-template <int N>
-__global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
-                                                     int c0, double tol_o, int cap_o, int CS, double* fac_n,
-                                                     int* rank_n, const double* Win, double* Wout, double* Wkeep,
-                                                     double rel_thr, double abs_fac, double drop) {
-  constexpr int NT = kEigThreads;
-  constexpr int LD = N + 1;
-  constexpr int NH = N / 2;
-  constexpr int NBLK = NH * (NH + 1) / 2;
-  __shared__ double A[N * LD];
-  __shared__ double V[N * LD];
-  __shared__ double Tm[N * LD];
-  __shared__ double cs[NH], sn[NH], tt[NH];
-  __shared__ int pp[NH], qq[NH];
-  __shared__ int bi_[NBLK], bj_[NBLK];
-  __shared__ int order[N];
-  __shared__ int flag[2], s_conv;
-  __shared__ double s_tot;
-  __shared__ int s_rank;
-  const int m = blockIdx.x;
-  const int cl = m / 3, mode = m % 3;
-  const int cell = c0 + cl;
+}  // namespace
+
+// Eigensolver statistics: [0] matrices solved on the leading block, [1] on
+// the full matrix, [2] Jacobi sweeps run, [3] leading-block attempts that fell
+// back to the full matrix.
+__device__ unsigned long long g_eig_stats[4];
+
+namespace {
+
+// Parallel cyclic Jacobi on the n x n symmetric matrix A (leading dimension
+// lda; n even), rotations accumulated into the columns of V (nv rows,
+// leading dimension ldv).  Round-robin ordering: n/2 disjoint pairs per
+// round, n-1 rounds per sweep; a pair rotates when |a_pq| exceeds both
+// rel_thr sqrt(|a_pp a_qq|) and abs_thr.  Convergence is checked by a
+// parallel scan of the off-diagonal elements before each sweep.  All
+// threads of the block call it.
+template <int NT, int NHMAX>
+__device__ void jacobi(double* A, int lda, double* V, int ldv, int nv, int n, double rel_thr, double abs_thr,
+                       double* cs, double* sn, double* tt, int* pp, int* qq, int* flag, int* conv) {
   const int lane = threadIdx.x;
-  const double* g = Gm + (size_t)m * N * N;
-  double* wk = Wkeep ? Wkeep + ((size_t)cell * 3 + mode) * N * N : nullptr;
-  for (int o = lane; o < N * N; o += NT) {
-    const int i = o / N, j = o % N;
-    A[i * LD + j] = g[o];
-    // V[i][j]: entry i of vector j
-    V[i * LD + j] = wk ? wk[j * N + i] : ((i == j) ? 1.0 : 0.0);
-  }
-  for (int b = lane; b < NBLK; b += NT) {
-    int I = 0, rem = b;
-    while (rem >= NH - I) { rem -= NH - I; ++I; }
-    bi_[b] = I;
-    bj_[b] = I + rem;
-  }
-  __syncthreads();
-  if (lane == 0) {
-    double t = 0.0;
-    for (int i = 0; i < N; ++i) t += A[i * LD + i];
-    s_tot = t;
-  }
-  if (wk) {
-    // A <- V^T A V through Tm = A V
-    for (int o = lane; o < N * N; o += NT) {
-      const int i = o / N, j = o % N;
-      double s = 0.0;
-      for (int k = 0; k < N; ++k) s += A[i * LD + k] * V[k * LD + j];
-      Tm[i * LD + j] = s;
-    }
-    __syncthreads();
-    for (int o = lane; o < N * N; o += NT) {
-      const int i = o / N, j = o % N;
-      if (j < i) continue;
-      double s = 0.0;
-      for (int k = 0; k < N; ++k) s += V[k * LD + i] * Tm[k * LD + j];
-      A[i * LD + j] = s;
-      A[j * LD + i] = s;
-    }
-  }
-  __syncthreads();
-  const double abs_thr = abs_fac * fabs(s_tot);
+  const int nh = n / 2;
+  const int nblk = nh * (nh + 1) / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    // converged when no off-diagonal element exceeds the rotation threshold
     if (lane == 0) {
-      s_conv = 1;
+      *conv = 1;
       flag[0] = 0;
       flag[1] = 0;
     }
     __syncthreads();
-    for (int o = lane; o < N * N; o += NT) {
-      const int i = o / N, j = o % N;
+    for (int o = lane; o < n * n; o += NT) {
+      const int i = o / n, j = o % n;
       if (j <= i) continue;
-      const double apq = A[i * LD + j];
-      if (fabs(apq) > fmax(rel_thr * sqrt(fabs(A[i * LD + i] * A[j * LD + j])), abs_thr)) s_conv = 0;
+      const double apq = A[i * lda + j];
+      if (fabs(apq) > fmax(rel_thr * sqrt(fabs(A[i * lda + i] * A[j * lda + j])), abs_thr)) *conv = 0;
     }
     __syncthreads();
-    if (s_conv) break;
-    for (int r = 0; r < N - 1; ++r) {
+    if (*conv) break;
+    if (lane == 0) atomicAdd(&g_eig_stats[2], 1ull);
+    for (int r = 0; r < n - 1; ++r) {
       // flag[r & 1]: some pair of round r rotates.  The other flag is cleared
       // for the next round; its readers (round r - 1) have all passed that
       // round's last barrier, or read a value that is already 0.
       const int f = r & 1;
-      if (lane < NH) {
+      if (lane < nh) {
         int p, q;
         if (lane == 0) {
           p = 0;
-          q = 1 + r % (N - 1);
+          q = 1 + r % (n - 1);
         } else {
-          p = 1 + (r + lane) % (N - 1);
-          q = 1 + (r + N - 1 - lane) % (N - 1);
+          p = 1 + (r + lane) % (n - 1);
+          q = 1 + (r + n - 1 - lane) % (n - 1);
         }
         if (p > q) { const int t = p; p = q; q = t; }
-        const double app = A[p * LD + p], aqq = A[q * LD + q], apq = A[p * LD + q];
+        const double app = A[p * lda + p], aqq = A[q * lda + q], apq = A[p * lda + q];
         double c = 1.0, s = 0.0, t = 0.0;
         if (fabs(apq) > fmax(rel_thr * sqrt(fabs(app * aqq)), abs_thr) && apq != 0.0) {
           const double th = (aqq - app) / (2.0 * apq);
@@ -148,73 +113,269 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int
       if (lane == 0) flag[f ^ 1] = 0;
       __syncthreads();
       if (!flag[f]) continue;
-      for (int b = lane; b < NBLK; b += NT) {
-        const int I = bi_[b], J = bj_[b];
+      for (int b = lane; b < nblk; b += NT) {
+        int I = 0, rem = b;
+        while (rem >= nh - I) { rem -= nh - I; ++I; }
+        const int J = I + rem;
         if (I == J) {
           const double t = tt[I];
           if (t != 0.0) {
             const int pI = pp[I], qI = qq[I];
-            const double apq = A[pI * LD + qI];
-            A[pI * LD + pI] -= t * apq;
-            A[qI * LD + qI] += t * apq;
-            A[pI * LD + qI] = 0.0;
-            A[qI * LD + pI] = 0.0;
+            const double apq = A[pI * lda + qI];
+            A[pI * lda + pI] -= t * apq;
+            A[qI * lda + qI] += t * apq;
+            A[pI * lda + qI] = 0.0;
+            A[qI * lda + pI] = 0.0;
           }
         } else {
           const double sI = sn[I], sJ = sn[J];
           if (sI == 0.0 && sJ == 0.0) continue;
           const int pI = pp[I], qI = qq[I], pJ = pp[J], qJ = qq[J];
           const double cI = cs[I], cJ = cs[J];
-          const double a = A[pI * LD + pJ], bb = A[pI * LD + qJ];
-          const double cc = A[qI * LD + pJ], dd = A[qI * LD + qJ];
+          const double a = A[pI * lda + pJ], bb = A[pI * lda + qJ];
+          const double cc = A[qI * lda + pJ], dd = A[qI * lda + qJ];
           const double a1 = cJ * a - sJ * bb, b1 = sJ * a + cJ * bb;
           const double c1 = cJ * cc - sJ * dd, d1 = sJ * cc + cJ * dd;
           const double a2 = cI * a1 - sI * c1, c2 = sI * a1 + cI * c1;
           const double b2 = cI * b1 - sI * d1, d2 = sI * b1 + cI * d1;
-          A[pI * LD + pJ] = a2; A[pJ * LD + pI] = a2;
-          A[pI * LD + qJ] = b2; A[qJ * LD + pI] = b2;
-          A[qI * LD + pJ] = c2; A[pJ * LD + qI] = c2;
-          A[qI * LD + qJ] = d2; A[qJ * LD + qI] = d2;
+          A[pI * lda + pJ] = a2; A[pJ * lda + pI] = a2;
+          A[pI * lda + qJ] = b2; A[qJ * lda + pI] = b2;
+          A[qI * lda + pJ] = c2; A[pJ * lda + qI] = c2;
+          A[qI * lda + qJ] = d2; A[qJ * lda + qI] = d2;
         }
       }
-      for (int it = lane; it < N * NH; it += NT) {
-        const int row = it % N, J = it / N;
+      for (int it = lane; it < nv * nh; it += NT) {
+        const int row = it % nv, J = it / nv;
         const double c = cs[J], s = sn[J];
         if (s == 0.0) continue;
         const int p = pp[J], q = qq[J];
-        const double v1 = V[row * LD + p], v2 = V[row * LD + q];
-        V[row * LD + p] = c * v1 - s * v2;
-        V[row * LD + q] = s * v1 + c * v2;
+        const double v1 = V[row * ldv + p], v2 = V[row * ldv + q];
+        V[row * ldv + p] = c * v1 - s * v2;
+        V[row * ldv + q] = s * v1 + c * v2;
       }
       __syncthreads();
     }
   }
   __syncthreads();
-  // sort eigenvalues, descending (stable on ties); the identity order first so
-  // that every entry stays a valid index even if a value is not a number
-  if (lane < N) order[lane] = lane;
+}
+
+// Descending order of the n values d[0..n) (stable on ties) into order[];
+// the identity first so every entry stays a valid index.
+template <int NT>
+__device__ void sort_desc(const double* d, int stride, int n, int* order) {
+  const int lane = threadIdx.x;
+  for (int i = lane; i < n; i += NT) order[i] = i;
   __syncthreads();
-  if (lane < N) {
-    const double li = A[lane * LD + lane];
+  for (int i = lane; i < n; i += NT) {
+    const double li = d[i * stride];
     int pos = 0;
-    for (int j = 0; j < N; ++j) {
-      const double lj = A[j * LD + j];
-      pos += (lj > li) || (lj == li && j < lane);
+    for (int j = 0; j < n; ++j) {
+      const double lj = d[j * stride];
+      pos += (lj > li) || (lj == li && j < i);
     }
-    if (pos < N) order[pos] = lane;
+    if (pos < n) order[pos] = i;
   }
   __syncthreads();
+}
+
+// The truncation rule: smallest r >= 1 with extra + sum_{k >= r} lam_k <= thr
+// (lam sorted descending, n of them), or with drop > 0 the count of values
+// above drop^2 lam_0; then capped.
+__device__ inline int choose_rank(const double* lam, int stride, const int* order, int n, double extra, double thr,
+                                  double drop, int cap) {
+  int r = n;
+  if (drop > 0.0) {
+    const double l0 = lam[order[0] * stride];
+    r = 0;
+    for (int k = 0; k < n; ++k)
+      if (lam[order[k] * stride] > drop * drop * l0) ++r;
+  } else {
+    double tail = extra;
+    if (tail > thr) return cap < n ? cap : n;  // the discarded block alone exceeds the budget
+    for (int k = n - 1; k >= 1; --k) {
+      tail += lam[order[k] * stride];
+      if (tail <= thr) r = k;
+      else break;
+    }
+  }
+  if (r > cap) r = cap;
+  if (r < 1) r = 1;
+  return r;
+}
+
+template <int N>
+__global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
+                                                     int c0, double tol_o, int cap_o, int CS, double* fac_n,
+                                                     int* rank_n, const double* Win, double* Wout, double* Wkeep,
+                                                     double rel_thr, double abs_fac, double drop,
+                                                     const int* rank_prev, int lead) {
+  constexpr int NT = kEigThreads;
+  constexpr int LD = N + 1;
+  constexpr int NH = N / 2;
+  __shared__ double A[N * LD];
+  __shared__ double V[N * LD];
+  __shared__ double Tm[N * LD];
+  __shared__ double cs[NH], sn[NH], tt[NH];
+  __shared__ int pp[NH], qq[NH];
+  __shared__ int order[N];
+  __shared__ int flag[2], s_conv;
+  __shared__ double s_tot, s_aux;
+  __shared__ int s_rank, s_k, s_fast;
+  const int m = blockIdx.x;
+  const int cl = m / 3, mode = m % 3;
+  const int cell = c0 + cl;
+  const int lane = threadIdx.x;
+  const double* g = Gm + (size_t)m * N * N;
+  double* wk = Wkeep ? Wkeep + ((size_t)cell * 3 + mode) * N * N : nullptr;
+  double tol = tol_o;
+  int cap = cap_o;
+  if (inst) {
+    const InstParams P = ip[inst[cell]];
+    tol = P.tol;
+    cap = P.cap;
+  }
+  for (int o = lane; o < N * N; o += NT) {
+    const int i = o / N, j = o % N;
+    A[i * LD + j] = g[o];
+    // V[i][j]: entry i of vector j
+    V[i * LD + j] = wk ? wk[j * N + i] : ((i == j) ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (lane == 0) {
+    double t = 0.0;
+    for (int i = 0; i < N; ++i) t += A[i * LD + i];
+    s_tot = t;
+    s_fast = 0;
+    int k = N;
+    if (wk && lead > 0 && rank_prev) {
+      const int rp = rank_prev[3 * cell + mode];
+      k = (rp < 1 ? 1 : rp) + lead;
+      k += k & 1;
+      if (k > N) k = N;
+    }
+    s_k = k;
+  }
+  __syncthreads();
+  const double thr = tol * tol * s_tot / 3.0;
+  const double abs_thr = abs_fac * fabs(s_tot);
+  const int k = s_k;
+  if (k < N) {
+    // ---- leading block of the previous basis: B = W_k^T G W_k -------------
+    for (int o = lane; o < N * k; o += NT) {
+      const int i = o / k, j = o % k;
+      double s = 0.0;
+      for (int t = 0; t < N; ++t) s += A[i * LD + t] * V[t * LD + j];
+      Tm[i * LD + j] = s;
+    }
+    __syncthreads();
+    for (int o = lane; o < k * k; o += NT) {
+      const int i = o / k, j = o % k;
+      if (j < i) continue;
+      double s = 0.0;
+      for (int t = 0; t < N; ++t) s += V[t * LD + i] * Tm[t * LD + j];
+      A[i * LD + j] = s;  // G is no longer needed on this path
+      A[j * LD + i] = s;
+    }
+    __syncthreads();
+    if (lane == 0) {
+      double tb = 0.0;
+      for (int i = 0; i < k; ++i) tb += A[i * LD + i];
+      const double tail = s_tot - tb;
+      s_aux = tail > 0.0 ? tail : 0.0;
+      // the rest of the spectrum carries a negligible share of the trace
+      s_fast = (drop == 0.0 && s_aux <= 1e-3 * thr) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_fast) {
+      for (int o = lane; o < k * k; o += NT) Tm[(o / k) * LD + o % k] = (o / k == o % k) ? 1.0 : 0.0;
+      __syncthreads();
+      jacobi<NT, NH>(A, LD, Tm, LD, k, k, rel_thr, abs_thr, cs, sn, tt, pp, qq, flag, &s_conv);
+      sort_desc<NT>(A, LD + 1, k, order);
+      if (lane == 0) {
+        const int r = choose_rank(A, LD + 1, order, k, s_aux, thr, 0.0, cap);
+        s_rank = r;
+        s_fast = (r <= k - 2) ? 1 : 0;  // keep a margin inside the block
+      }
+      __syncthreads();
+    }
+    if (lane == 0) atomicAdd(&g_eig_stats[s_fast ? 0 : 3], 1ull);
+    if (s_fast) {
+      // new leading vectors W_k V_k (sorted) into A's storage; tail vectors unchanged
+      for (int o = lane; o < N * k; o += NT) {
+        const int i = o / k, j = o % k;
+        double s = 0.0;
+        const int jj = order[j];
+        for (int t = 0; t < k; ++t) s += V[i * LD + t] * Tm[t * LD + jj];
+        A[i * LD + j] = s;
+      }
+      __syncthreads();
+      if (wk) {
+        for (int o = lane; o < N * k; o += NT) {
+          const int j = o / N, i = o % N;
+          wk[j * N + i] = A[i * LD + j];
+        }
+      }
+      const int r = s_rank;
+      if (lane == 0) rank_n[3 * cell + mode] = r;
+      double* out = fac_n + ((size_t)cell * 3 + mode) * CS * N;
+      for (int c = 0; c < CS; ++c) {
+        if (c < r) {
+          if (lane == 0) {
+            double best = -1.0;
+            int bi = 0;
+            for (int i = 0; i < N; ++i) {
+              const double v = fabs(A[i * LD + c]);
+              if (v > best) { best = v; bi = i; }
+            }
+            cs[0] = (A[bi * LD + c] < 0.0) ? -1.0 : 1.0;
+          }
+          __syncthreads();
+          const double sg = cs[0];
+          for (int i = lane; i < N; i += NT) out[c * N + i] = sg * A[i * LD + c];
+          __syncthreads();
+        } else {
+          for (int i = lane; i < N; i += NT) out[c * N + i] = 0.0;
+        }
+      }
+      return;
+    }
+    // fall back to the full matrix
+    for (int o = lane; o < N * N; o += NT) A[(o / N) * LD + o % N] = g[o];
+    __syncthreads();
+  }
+  if (wk) {
+    // ---- full warm start: A <- V^T G V through Tm = G V --------------------
+    for (int o = lane; o < N * N; o += NT) {
+      const int i = o / N, j = o % N;
+      double s = 0.0;
+      for (int t = 0; t < N; ++t) s += A[i * LD + t] * V[t * LD + j];
+      Tm[i * LD + j] = s;
+    }
+    __syncthreads();
+    for (int o = lane; o < N * N; o += NT) {
+      const int i = o / N, j = o % N;
+      if (j < i) continue;
+      double s = 0.0;
+      for (int t = 0; t < N; ++t) s += V[t * LD + i] * Tm[t * LD + j];
+      A[i * LD + j] = s;
+      A[j * LD + i] = s;
+    }
+    __syncthreads();
+  }
+  if (lane == 0) atomicAdd(&g_eig_stats[1], 1ull);
+  jacobi<NT, NH>(A, LD, V, LD, N, N, rel_thr, abs_thr, cs, sn, tt, pp, qq, flag, &s_conv);
+  sort_desc<NT>(A, LD + 1, N, order);
   if (wk) {
     for (int o = lane; o < N * N; o += NT) {
-      const int k = o / N, i = o % N;
-      wk[o] = V[i * LD + order[k]];
+      const int kk = o / N, i = o % N;
+      wk[o] = V[i * LD + order[kk]];
     }
   }
   if (Wout) {
     // full sorted basis (premultiplied by Win when given), no truncation
     double* out = Wout + (size_t)m * N * N;
     for (int o = lane; o < N * N; o += NT) {
-      const int k = o / N, i = o % N, j = order[k];
+      const int kk = o / N, i = o % N, j = order[kk];
       double v;
       if (Win) {
         const double* w = Win + (size_t)m * N * N;
@@ -228,34 +389,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int
     return;
   }
   if (lane == 0) {
-    double tol = tol_o;
-    int cap = cap_o;
-    if (inst) {
-      const InstParams P = ip[inst[cell]];
-      tol = P.tol;
-      cap = P.cap;
-    }
-    double tot = 0.0;
-    for (int i = 0; i < N; ++i) tot += A[order[i] * LD + order[i]];
-    const double thr = tol * tol * tot / 3.0;
-    int r = N;
-    if (drop > 0.0) {
-      // keep singular values above drop * sigma_1 (eigenvalues above drop^2 lambda_1)
-      const double l0 = A[order[0] * LD + order[0]];
-      r = 0;
-      for (int k = 0; k < N; ++k)
-        if (A[order[k] * LD + order[k]] > drop * drop * l0) ++r;
-    } else {
-      // smallest r >= 1 with sum_{k >= r} lambda_k <= thr
-      double tail = 0.0;
-      for (int k = N - 1; k >= 1; --k) {
-        tail += A[order[k] * LD + order[k]];
-        if (tail <= thr) r = k;
-        else break;
-      }
-    }
-    if (r > cap) r = cap;
-    if (r < 1) r = 1;
+    const int r = choose_rank(A, LD + 1, order, N, 0.0, thr, drop, cap);
     s_rank = r;
     rank_n[3 * cell + mode] = r;
   }
@@ -263,9 +397,9 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int
   const int r = s_rank;
   double* out = fac_n + ((size_t)cell * 3 + mode) * CS * N;
   double* vec = Tm;
-  for (int k = 0; k < CS; ++k) {
-    if (k < r) {
-      const int j = order[k];
+  for (int c = 0; c < CS; ++c) {
+    if (c < r) {
+      const int j = order[c];
       for (int i = lane; i < N; i += NT) {
         double v;
         if (Win) {
@@ -290,10 +424,10 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int
       }
       __syncthreads();
       const double sg = cs[0];
-      for (int i = lane; i < N; i += NT) out[k * N + i] = sg * vec[i];
+      for (int i = lane; i < N; i += NT) out[c * N + i] = sg * vec[i];
       __syncthreads();
     } else {
-      for (int i = lane; i < N; i += NT) out[k * N + i] = 0.0;
+      for (int i = lane; i < N; i += NT) out[c * N + i] = 0.0;
     }
   }
 }
@@ -320,11 +454,11 @@ __global__ void k_identity_basis(int N, size_t count, double* W) {
 hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
                       double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
                       const double* Win, double* Wout, double* Wkeep, double rel_thr, double abs_fac,
-                      hipStream_t s, double drop) {
+                      hipStream_t s, double drop, const int* rank_prev, int lead) {
   if (count <= 0) return hipSuccess;
   dim3 grid(3 * count), blk(kEigThreads);
 #define TK_EIG(NN) hipLaunchKernelGGL(k_eig<NN>, grid, blk, 0, s, G, inst, ip, c0, tol_override, cap_override, CS, \
-                                      fac_n, rank_n, Win, Wout, Wkeep, rel_thr, abs_fac, drop)
+                                      fac_n, rank_n, Win, Wout, Wkeep, rel_thr, abs_fac, drop, rank_prev, lead)
   switch (N) {
     case 16: TK_EIG(16); break;
     case 24: TK_EIG(24); break;
@@ -352,5 +486,16 @@ hipError_t launch_absxi(int N, int count, const double* normals, double xi_min, 
   const int ne = N * N * N;
   hipLaunchKernelGGL(k_absxi, dim3((ne + 255) / 256, count), dim3(256), 0, s, N, normals, xi_min, dxi, X);
   return hipGetLastError();
+}
+}  // namespace tk
+
+namespace tk {
+hipError_t eig_stats(unsigned long long* out, bool reset) {
+  hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_eig_stats), sizeof(unsigned long long) * 4);
+  if (e == hipSuccess && reset) {
+    unsigned long long z[4] = {0, 0, 0, 0};
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_eig_stats), z, sizeof(z));
+  }
+  return e;
 }
 }  // namespace tk

@@ -88,80 +88,108 @@ __global__ __launch_bounds__(kPM) void k_plain_moments(DevPlain d) {
   }
 }
 
-// One thread updates EPT consecutive grid nodes of one cell; the per-cell
-// constants (f_S parameters, face coefficients) are computed once per
-// workgroup.  Reads the cell and its six far sides once per node.
+// One workgroup updates a chunk of one cell's grid nodes.  Per-cell 1-D
+// tables are built once per workgroup: the Maxwellian factors of f_S
+// (f_M = m_1(i1) m_2(i2) m_3(i3)), the separable outflow weight
+// d_a(i) = -sum_{faces on axis a} (dt A/V) max(s xi_i, 0) and each face's
+// inflow scaling b_l(i) = (dt A/V) max(-s xi_i, 0); per node only
+// polynomial arithmetic remains (in the storage precision).
 template <int N, typename T>
 __global__ __launch_bounds__(kPM) void k_plain_step(DevPlain d) {
   constexpr int NE = N * N * N;
   constexpr int EPT = 4;
-  __shared__ double s_c[16];
-  __shared__ double s_coef[kSlots];
+  __shared__ T s_m[3][N];       // Maxwellian 1-D factors
+  __shared__ T s_v[3][N];       // xi_i - u_a
+  __shared__ T s_d[3][N];       // separable own-cell weights
+  __shared__ T s_b[kSlots][N];  // inflow scalings of the six faces
+  __shared__ T s_c[8];
   __shared__ int s_nb[kSlots];
-  __shared__ int8_t s_kind[kSlots], s_axis[kSlots], s_sig[kSlots];
+  __shared__ int8_t s_kind[kSlots], s_axis[kSlots];
   const int c = blockIdx.x;
+  const int tid = threadIdx.x;
   const InstParams P = d.ip[d.inst[c]];
-  if (threadIdx.x == 0) {
-    const double* M = d.macro + 8 * (size_t)c;
-    const double nu = d.nu[c];
-    const double RT = P.Rg * M[4];
-    s_c[0] = M[0] / pow(2.0 * M_PI * RT, 1.5);               // f_M amplitude
-    s_c[1] = 1.0 / (2.0 * RT);                               // 1 / (2 R_g T)
-    s_c[2] = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * M[0] * RT * RT);  // A_s
-    s_c[3] = P.dt * nu;
-    for (int a = 0; a < 3; ++a) { s_c[4 + a] = M[1 + a]; s_c[7 + a] = M[5 + a]; }
+  const double* M = d.macro + 8 * (size_t)c;
+  if (tid < kSlots) {
+    s_kind[tid] = d.slot_kind[kSlots * c + tid];
+    s_axis[tid] = d.slot_axis[kSlots * c + tid];
+    s_nb[tid] = d.slot_nb[kSlots * c + tid];
+  }
+  const double RT = P.Rg * M[4];
+  const double nu = d.nu[c];
+  for (int o = tid; o < 3 * N; o += kPM) {
+    const int a = o / N, i = o % N;
+    const double x = P.xi_min + i * P.dxi;
+    const double v = x - M[1 + a];
+    s_m[a][i] = (T)(cbrt(M[0]) / sqrt(2.0 * M_PI * RT) * exp(-v * v / (2.0 * RT)));
+    s_v[a][i] = (T)v;
+    double w = 0.0;
     for (int l = 0; l < kSlots; ++l) {
-      s_kind[l] = d.slot_kind[kSlots * c + l];
-      s_axis[l] = d.slot_axis[kSlots * c + l];
-      s_sig[l] = d.slot_sig[kSlots * c + l];
-      s_coef[l] = d.slot_coef[kSlots * c + l];
-      s_nb[l] = d.slot_nb[kSlots * c + l];
+      if (d.slot_kind[kSlots * c + l] == SK_NONE || d.slot_axis[kSlots * c + l] != a) continue;
+      w -= d.slot_coef[kSlots * c + l] * fmax((double)d.slot_sig[kSlots * c + l] * x, 0.0);
     }
+    s_d[a][i] = (T)w;
+  }
+  for (int o = tid; o < kSlots * N; o += kPM) {
+    const int l = o / N, i = o % N;
+    const int8_t kind = d.slot_kind[kSlots * c + l];
+    double b = 0.0;
+    if (kind != SK_NONE) {
+      const int a = d.slot_axis[kSlots * c + l];
+      const double x = P.xi_min + i * P.dxi;
+      b = d.slot_coef[kSlots * c + l] * fmax(-(double)d.slot_sig[kSlots * c + l] * x, 0.0);
+      if (kind == SK_WALL) b *= d.nw[kSlots * c + l];
+      (void)a;
+    }
+    s_b[l][i] = (T)b;
+  }
+  if (tid == 0) {
+    s_c[0] = (T)(1.0 - P.dt * nu);                                  // 1 - dt nu
+    s_c[1] = (T)(P.dt * nu);                                        // dt nu
+    s_c[2] = (T)(2.0 * (1.0 - P.Pr) / (5.0 * P.m * M[0] * RT * RT));  // A_s
+    s_c[3] = (T)(1.0 / (2.0 * RT));                                 // beta
+    for (int a = 0; a < 3; ++a) s_c[4 + a] = (T)M[5 + a];            // q
   }
   __syncthreads();
-  const int e0 = (blockIdx.y * kPM + threadIdx.x) * EPT;
+  const int e0 = (blockIdx.y * kPM + tid) * EPT;
   if (e0 >= NE) return;
   const T* f = (const T*)d.f;
-  const double amp = s_c[0], ib = s_c[1], As = s_c[2], dtnu = s_c[3];
+  T* fo = (T*)d.f_n;
+  const T c1 = s_c[0], dtnu = s_c[1], As = s_c[2], beta = s_c[3];
+  const T q0 = s_c[4], q1 = s_c[5], q2 = s_c[6];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = e0 + q;
-    const int idx[3] = {e % N, (e / N) % N, e / (N * N)};
-    const double x[3] = {P.xi_min + idx[0] * P.dxi, P.xi_min + idx[1] * P.dxi, P.xi_min + idx[2] * P.dxi};
-    const double own = (double)f[(size_t)c * NE + e];
-    const double v[3] = {x[0] - s_c[4], x[1] - s_c[5], x[2] - s_c[6]};
-    const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    const double qv = s_c[7] * v[0] + s_c[8] * v[1] + s_c[9] * v[2];
-    const double fs = amp * exp(-v2 * ib) * (1.0 + As * qv * (v2 * ib - 2.5));
-    double w = 1.0 - dtnu;
-    double acc = dtnu * fs;
+  for (int qn = 0; qn < EPT; ++qn) {
+    const int e = e0 + qn;
+    const int i1 = e % N, i2 = (e / N) % N, i3 = e / (N * N);
+    const int idx[3] = {i1, i2, i3};
+    const T own = f[(size_t)c * NE + e];
+    const T v1 = s_v[0][i1], v2 = s_v[1][i2], v3 = s_v[2][i3];
+    const T vv = v1 * v1 + v2 * v2 + v3 * v3;
+    const T fs = s_m[0][i1] * s_m[1][i2] * s_m[2][i3] *
+                 ((T)1 + As * (q0 * v1 + q1 * v2 + q2 * v3) * (beta * vv - (T)2.5));
+    T acc = (c1 + s_d[0][i1] + s_d[1][i2] + s_d[2][i3]) * own + dtnu * fs;
+#pragma unroll
     for (int l = 0; l < kSlots; ++l) {
       const int8_t kind = s_kind[l];
       if (kind == SK_NONE) continue;
       const int a = s_axis[l];
-      const double sg = (double)s_sig[l];
-      const double coef = s_coef[l];
-      w -= coef * fmax(sg * x[a], 0.0);
-      const double b = coef * fmax(-sg * x[a], 0.0);
-      if (b == 0.0) continue;
-      const int nb = s_nb[l];
-      double g;
+      const T b = s_b[l][idx[a]];
+      if (b == (T)0) continue;
+      T g;
       if (kind == SK_INTERIOR) {
-        g = (double)f[(size_t)nb * NE + e];
+        g = f[(size_t)s_nb[l] * NE + e];
       } else if (kind == SK_OUTFLOW) {
         g = own;
       } else if (kind == SK_SYM) {
-        int r[3] = {idx[0], idx[1], idx[2]};
+        int r[3] = {i1, i2, i3};
         r[a] = N - 1 - r[a];
-        g = (double)f[(size_t)c * NE + r[0] + N * (r[1] + N * r[2])];
+        g = f[(size_t)c * NE + r[0] + N * (r[1] + N * r[2])];
       } else {
-        const double* bf = d.bc_fac + (size_t)nb * 3 * N;
-        g = bf[idx[0]] * bf[N + idx[1]] * bf[2 * N + idx[2]];
-        if (kind == SK_WALL) g *= d.nw[kSlots * c + l];
+        const double* bf = d.bc_fac + (size_t)s_nb[l] * 3 * N;
+        g = (T)(bf[i1] * bf[N + i2] * bf[2 * N + i3]);
       }
       acc += b * g;
     }
-    ((T*)d.f_n)[(size_t)c * NE + e] = (T)(w * own + acc);
+    fo[(size_t)c * NE + e] = acc;
   }
 }
 

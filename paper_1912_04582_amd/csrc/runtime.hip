@@ -606,7 +606,7 @@ static tk_status state_step_once(tk_state* st) {
     prof_begin(ctx, KID_EIG, &ev);
     if (st->mixed) {
       e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
-                     nullptr, st->Wkeep, 1e-12, 1e-16, q);
+                     nullptr, st->Wkeep, 1e-12, 1e-16, q, 0.0, st->warm ? d.rank : nullptr, st->warm ? 8 : 0);
     } else {
       // FP64 path: first basis, Gram of the rotated unfoldings, final basis
       e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
@@ -624,6 +624,7 @@ static tk_status state_step_once(tk_state* st) {
     if (e != hipSuccess) return ctx_hip(ctx, e, "project");
   }
   st->cur ^= 1;
+  st->warm = true;
   return TK_OK;
 }
 
@@ -759,6 +760,18 @@ tk_status tk_prof_get(tk_ctx* ctx, const char* kernel, double* total_ms, int64_t
       return TK_OK;
     }
   return ctx_fail(ctx, TK_ENOTFOUND, std::string("unknown kernel family ") + kernel);
+}
+
+tk_status tk_prof_eig(tk_ctx* ctx, int64_t* out4, int32_t reset) {
+  if (!ctx || !out4) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  if (ctx->device < 0) return ctx_fail(ctx, TK_EDEVICE, "host-only context");
+  unsigned long long v[4];
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = eig_stats(v, reset != 0);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "eig stats");
+  for (int i = 0; i < 4; ++i) out4[i] = (int64_t)v[i];
+  return TK_OK;
 }
 
 tk_status tk_prof_reset(tk_ctx* ctx) {

@@ -92,6 +92,7 @@ struct tk_state {
   int* d_est_rank = nullptr;     // [n_est][3]
   double* Wb = nullptr;     // first-pass bases of the FP64 refinement
   double* Wkeep = nullptr;  // [nc][3][N][N] previous full eigenbases (warm start)
+  bool warm = false;        // Wkeep holds real bases (after the first step)
   // plain comparator storage
   void* pf[2] = {nullptr, nullptr};
 };

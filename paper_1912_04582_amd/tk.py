@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "TK_OK", 1: "TK_PENDING", -1: "TK_EINVAL", -2: "TK_ENOMEM", -
 
 EXPORTED = [
     "tk_ctx_create", "tk_ctx_destroy", "tk_last_error", "tk_sync", "tk_prof_enable", "tk_prof_get",
-    "tk_prof_reset", "tk_mesh_load", "tk_mesh_destroy", "tk_state_init", "tk_state_init_batch",
+    "tk_prof_reset", "tk_prof_eig", "tk_mesh_load", "tk_mesh_destroy", "tk_state_init", "tk_state_init_batch",
     "tk_state_destroy", "tk_state_info", "tk_state_dt", "tk_moments", "tk_step", "tk_step_async",
     "tk_state_ranks", "tk_state_export", "tk_round_tucker", "tk_plain_init", "tk_serve_create",
     "tk_serve_submit", "tk_serve_poll", "tk_serve_destroy",
@@ -90,6 +90,7 @@ def lib():
             "tk_prof_enable": [P, C.c_int32],
             "tk_prof_get": [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
             "tk_prof_reset": [P],
+            "tk_prof_eig": [P, C.POINTER(C.c_int64), C.c_int32],
             "tk_mesh_load": [P, C.POINTER(tk_mesh_desc), C.POINTER(P)],
             "tk_mesh_destroy": [P],
             "tk_state_init": [P, P, C.POINTER(tk_params), C.POINTER(C.c_double), C.POINTER(P)],
@@ -190,6 +191,11 @@ class Context:
         ms, n = C.c_double(), C.c_int64()
         _check(lib().tk_prof_get(self.h, kernel.encode(), C.byref(ms), C.byref(n)), self.h)
         return ms.value, n.value
+
+    def eig_stats(self, reset=False):
+        v = (C.c_int64 * 4)()
+        _check(lib().tk_prof_eig(self.h, v, 1 if reset else 0), self.h)
+        return {"lead": v[0], "full": v[1], "sweeps": v[2], "fallback": v[3]}
 
     def round_tucker(self, tensors, tol, cap):
         """tk_round_tucker on a list of (core, [U1, U2, U3]) numpy Tucker tensors."""
