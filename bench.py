@@ -82,6 +82,25 @@ def project_flops(N, ranks):
     return float((2 * (r1 * N ** 3 + r1 * r2 * N * N + r1 * r2 * r3 * N)).sum())
 
 
+def measured_traffic(workload_name, fam):
+    """HBM bytes per launch of a kernel family from the committed counter
+    summaries (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when
+    there is none for this workload or the kernel's source has changed since."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+        with open(path) as fh:
+            d = json.load(fh)
+        k = d.get("kernels", {}).get(fam)
+        if d.get("workload") != workload_name or not k:
+            continue
+        with open(os.path.join(ROOT, k["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != k["sha256"]:
+                return None
+        return k["fetch_bytes"] + k["write_bytes"]
+    return None
+
+
 def roofline(fam, cfg, mesh, res, steps):
     """Achieved rate of one kernel family against its bound, per launch."""
     N, nc = cfg["N"], mesh["n_cells"]
@@ -102,7 +121,7 @@ def roofline(fam, cfg, mesh, res, steps):
         return None
     achieved = work / launches_per_step / per_launch_s / 1e12
     return {"bound": bound, "achieved": achieved, "peak": peak / 1e12, "unit": unit,
-            "frac": achieved / (peak / 1e12), "traffic": None, "kernel": fam,
+            "frac": achieved / (peak / 1e12), "traffic": measured_traffic(cfg["name"], fam), "kernel": fam,
             "avg_launch_ms": per_launch_s * 1e3, "launches_per_step": launches_per_step}
 
 
