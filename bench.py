@@ -199,10 +199,15 @@ def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True):
     ctx = tk.Context(0)
     try:
         tm = tk.Mesh(ctx, mesh)
+        # untimed: the pass-size trial steps (the choice is kept on the
+        # context for the timed state of the same shape), then the warm-up
+        w = tk.State(ctx, tm, cfg, m0, plain=plain)
+        trials = w.tune()
+        if not plain:
+            log(f"  rounding pass: {w.chunk()[0]} cells (of {w.chunk()[1]}), chosen over {trials} trial steps")
         if warmup:
-            w = tk.State(ctx, tm, cfg, m0, plain=plain)
             w.step(warmup)
-            w.close()
+        w.close()
         st = tk.State(ctx, tm, cfg, m0, plain=plain)
         ctx.sync()
         ctx.prof_reset()
@@ -226,7 +231,7 @@ def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True):
     return dict(seconds=t1 - t0, prof=prof_ms, ranks0=r0, ranks1=r1, compression=C)
 
 
-def run_batch(steps, warmup, count):
+def run_batch(steps, warmup, count, prof_steps=3):
     """The batched workload: independent periodic boxes grouped by N into
     one state per N; every state advances `steps` steps."""
     insts = synth.configs.batch_instances(count=count)
@@ -240,30 +245,39 @@ def run_batch(steps, warmup, count):
         for N, items in sorted(groups.items()):
             ms = [tk.Mesh(ctx, m) for _, m, _ in items]
             meshes += ms
+            # untimed: pass-size trials on a throw-away state of the group
+            # (kept on the context for the timed state of the same shape)
+            w = tk.State(ctx, ms, [c for c, _, _ in items], [m0 for _, _, m0 in items])
+            w.tune()
             if warmup:
-                # a small state of the group's first instance loads the kernels
-                w = tk.State(ctx, ms[:1], [items[0][0]], [items[0][2]])
                 w.step(warmup)
-                w.close()
-            states.append(tk.State(ctx, ms, [c for c, _, _ in items], [m0 for _, _, m0 in items]))
+            w.close()
+            st = tk.State(ctx, ms, [c for c, _, _ in items], [m0 for _, _, m0 in items])
+            st.use_graph(True)
+            states.append(st)
         cells = sum(s.n_cells for s in states)
         ctx.sync()
-        ctx.prof_reset()
-        ctx.prof_enable(True)
         t0 = time.perf_counter()
         for st in states:
             st.step_async(steps)
         ctx.sync()
         t1 = time.perf_counter()
+        # kernel-family times from a few further eager steps with HIP events
+        ctx.prof_reset()
+        ctx.prof_enable(True)
+        for st in states:
+            st.step_async(prof_steps)
+        ctx.sync()
         ctx.prof_enable(False)
         prof = {f: ctx.prof_get(f) for f in ["moments", "expand", "gram", "eig", "project"]}
+        chunks = {st.n_cells: st.chunk()[0] for st in states}
         for st in states:
             st.close()
         for m in meshes:
             m.close()
     finally:
         ctx.close()
-    return dict(seconds=t1 - t0, cells=cells, prof=prof,
+    return dict(seconds=t1 - t0, cells=cells, prof=prof, prof_steps=prof_steps, chunks=chunks,
                 groups={N: (len(v), sum(m["n_cells"] for _, m, _ in v)) for N, v in groups.items()})
 
 
@@ -309,7 +323,8 @@ def run_serve(count, max_steps, seed=4):
     sat = serve_run(reqs, None)
     rate = 0.7 * count / sat["seconds"]
     paced = serve_run(reqs, rate)
-    return dict(saturated=sat, paced=paced, rate=rate, cells=[q[0]["n_cells"] for q in reqs])
+    half = serve_run(reqs, 0.5 * rate, seed=6)
+    return dict(saturated=sat, paced=paced, paced_half=half, rate=rate, cells=[q[0]["n_cells"] for q in reqs])
 
 
 def main():
@@ -359,7 +374,7 @@ def main():
                "vs_baseline": None, "dtype": "f32 terms + f64 rounding", "data": "synthetic",
                "config": {"workload": f"serving {a.serve_count} jittered-box requests",
                           "max_steps": a.serve_max_steps, "cells": r["cells"]}}
-        for key in ("saturated", "paced"):
+        for key in ("saturated", "paced", "paced_half"):
             q = r[key]
             out[key] = {"value": q["updates"] / q["seconds"], "seconds": q["seconds"],
                         "p50_latency_s": float(np.percentile(q["latency"], 50)),
@@ -368,6 +383,7 @@ def main():
             log(f"serve {key}: {out[key]['value']:.4g} cell-updates/s, p50 {out[key]['p50_latency_s']:.2f} s, "
                 f"p99 {out[key]['p99_latency_s']:.2f} s over {q['seconds']:.1f} s")
         out["arrival_rate_per_s"] = r["rate"]
+        out["arrival_rate_half_per_s"] = 0.5 * r["rate"]
         out["value"] = out["paced"]["value"]
         print(json.dumps(out), flush=True)
         return
@@ -378,7 +394,7 @@ def main():
         log(f"batch: {r['cells']} cells in {a.batch_count} instances {r['groups']}, "
             f"{1e3 * r['seconds'] / steps:.2f} ms/step, {value:.4g} cell-updates/s")
         for f, (ms, n) in r["prof"].items():
-            log(f"  {f:10s} {ms:10.2f} ms total over {n} launches")
+            log(f"  {f:10s} {ms:10.2f} ms total over {n} launches ({r['prof_steps']} eager profiled steps)")
         print(json.dumps({
             "metric": "Tucker S-model cell-updates/s (vs plain GPU step at 1e-5 rel err)", "value": value,
             "unit": "cell-updates/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup,
@@ -386,7 +402,9 @@ def main():
             "vs_baseline": None, "dtype": "f32 terms + f64 rounding", "data": "synthetic",
             "config": {"workload": f"batch of {a.batch_count} periodic boxes", "cells": r["cells"],
                        "groups_by_N": {str(k): v for k, v in r["groups"].items()}},
-            "kernel_ms_per_step": {f: ms / steps for f, (ms, n) in r["prof"].items()}}), flush=True)
+            "graph_replay": True, "rounding_pass_cells": {str(k): v for k, v in r["chunks"].items()},
+            "kernel_ms_per_step_eager": {f: ms / r["prof_steps"] for f, (ms, n) in r["prof"].items()}}),
+            flush=True)
         return
     cfg, mesh, m0 = workload(a.workload)
     nc = mesh["n_cells"]

@@ -161,6 +161,26 @@ tk_status tk_state_destroy(tk_state* st);
 tk_status tk_state_info(const tk_state* st, int32_t* n_cells, int32_t* n_instances);
 tk_status tk_state_dt(const tk_state* st, int32_t inst, double* dt);
 
+/* Cells per rounding pass (the expansion workspace holds one pass).
+ * cells = 0 lets the library choose: the first steps of the first state of
+ * a shape (N, precision, rank cap, cell count, face kind) on a context are
+ * timed with several pass sizes and the fastest is kept for every later
+ * state of that shape on the context.  cells > 0 fixes the pass size
+ * (TK_EINVAL above the allocated maximum).  Every choice computes the same
+ * bits: cells are independent within a pass.  tk_state_chunk reports the
+ * size in use and the allocated maximum.                                  */
+tk_status tk_state_set_chunk(tk_state* st, int32_t cells);
+tk_status tk_state_chunk(const tk_state* st, int32_t* cells, int32_t* max_cells);
+/* Run the remaining timed trial steps of the pass-size choice now (they
+ * advance the state like any step), then wait; steps_run (nullable)
+ * receives their number.  No-op when the size is chosen or fixed.        */
+tk_status tk_state_tune(tk_state* st, int32_t* steps_run);
+/* on != 0: after the first step, each step is replayed from a HIP graph
+ * captured from the same launches (one graph per buffer parity, captured
+ * again when the pass size changes); not while kernel timing is enabled.
+ * The results are those of the eager launches.                           */
+tk_status tk_state_use_graph(tk_state* st, int32_t on);
+
 /* Macroparameters of every cell, out[n_cells][8] = (n, u1, u2, u3, T, q1,
  * q2, q3), computed on the device in FP64 from the Tucker state (Alg. 2
  * steps 1-9 by Op5 convolutions).  Blocking.                              */

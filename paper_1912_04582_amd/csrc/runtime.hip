@@ -226,6 +226,11 @@ static double collision_freq(const tk_params& p, double n, double T) {
 
 void state_free(tk_state* st) {
   tk_ctx* ctx = st->ctx;
+  for (int p = 0; p < 2; ++p)
+    if (st->gexec[p]) (void)hipGraphExecDestroy(st->gexec[p]);
+  st->gexec[0] = st->gexec[1] = nullptr;
+  for (hipEvent_t e : st->tune_ev) (void)hipEventDestroy(e);
+  st->tune_ev.clear();
   for (void* p : st->allocs) ctx_free(ctx, p);
   st->allocs.clear();
 }
@@ -437,6 +442,7 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
   const size_t per = (size_t)N * N * N * tsz + 3 * (size_t)N * N * 8;
   size_t ws = std::min<size_t>(ctx->budget / 4, (size_t)4 << 30);
   st->chunk = (int)std::max<size_t>(1, std::min<size_t>(nc, ws / per));
+  st->chunk_max = st->chunk;
   // device allocations
   tk_status s = TK_OK;
   tk_state* S = st.get();
@@ -565,8 +571,50 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
   }
   if (e == hipSuccess) e = hipStreamSynchronize(q);
   if (e != hipSuccess) { state_free(S); return ctx_hip(ctx, e, "state init"); }
+  state_tune_begin(S);
   *out = st.release();
   return TK_OK;
+}
+
+// Key of the pass-size choice: states of one key run the same kernels on
+// the same amount of work.
+static std::string tune_key(const tk_state* st) {
+  return std::to_string(st->N) + (st->mixed ? "m" : "d") + (st->oblique ? "o" : "a") + std::to_string(st->CS) +
+         "/" + std::to_string(st->nc) + "/" + std::to_string(st->chunk_max);
+}
+
+// Candidate pass sizes: the allocated maximum, fixed sizes below it, and
+// the size whose FP32/FP64 workspace fits 192 MiB (the expansion is then
+// read back by the Gram and projection kernels from the 256 MiB last-level
+// cache rather than HBM).
+static std::vector<int> chunk_candidates(const tk_state* st) {
+  const size_t x = (size_t)st->N * st->N * st->N * (st->mixed ? 4 : 8);
+  std::vector<int> c = {st->chunk_max, 16384, 8192, 4096, 2048, (int)std::max<size_t>(256, (192u << 20) / x)};
+  std::vector<int> out;
+  for (int v : c)
+    if (v <= st->chunk_max && v >= 256 && std::find(out.begin(), out.end(), v) == out.end()) out.push_back(v);
+  std::sort(out.begin(), out.end());
+  return out;
+}
+
+void state_tune_begin(tk_state* st) {
+  st->tune = 0;
+  if (st->plain) return;
+  auto it = st->ctx->tuned_chunk.find(tune_key(st));
+  if (it != st->ctx->tuned_chunk.end()) {
+    st->chunk = it->second;
+    return;
+  }
+  st->tune_cand = chunk_candidates(st);
+  if (st->tune_cand.size() > 1) {
+    st->tune = 1;
+    st->tune_step = 0;
+  }
+}
+
+static void tune_events_free(tk_state* st) {
+  for (hipEvent_t e : st->tune_ev) (void)hipEventDestroy(e);
+  st->tune_ev.clear();
 }
 
 // one explicit step of every instance of the state
@@ -628,6 +676,78 @@ static tk_status state_step_once(tk_state* st) {
   return TK_OK;
 }
 
+// A step replayed from the graph captured for the current buffer parity.
+static tk_status state_step_graph(tk_state* st) {
+  tk_ctx* ctx = st->ctx;
+  hipStream_t q = ctx->stream;
+  const int p = st->cur;
+  hipError_t e = hipSuccess;
+  if (!st->gexec[p] || st->gchunk[p] != st->chunk) {
+    if (st->gexec[p]) (void)hipGraphExecDestroy(st->gexec[p]);
+    st->gexec[p] = nullptr;
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "graph capture");
+    const tk_status s = state_step_once(st);
+    e = hipStreamEndCapture(q, &g);
+    st->cur = p;
+    if (s != TK_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&st->gexec[p], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "graph instantiate");
+    st->gchunk[p] = st->chunk;
+  }
+  e = hipGraphLaunch(st->gexec[p], q);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "graph launch");
+  st->cur ^= 1;
+  return TK_OK;
+}
+
+// One step: a timed trial while the pass size is being chosen, a graph
+// replay when enabled, else eager launches.
+static tk_status state_step(tk_state* st) {
+  tk_ctx* ctx = st->ctx;
+  if (st->tune == 1) {
+    const int nc = (int)st->tune_cand.size();
+    st->chunk = st->tune_cand[st->tune_step % nc];
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return ctx_fail(ctx, TK_EDEVICE, "event");
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return ctx_fail(ctx, TK_EDEVICE, "event");
+    }
+    st->tune_ev.push_back(a);
+    st->tune_ev.push_back(b);
+    (void)hipEventRecord(a, ctx->stream);
+    const tk_status s = state_step_once(st);
+    (void)hipEventRecord(b, ctx->stream);
+    if (s != TK_OK) return s;
+    if (++st->tune_step == 2 * nc) {
+      // the smaller of two timings per candidate (the first step of a
+      // state starts its eigensolves cold)
+      std::vector<float> best(nc, 1e30f);
+      hipError_t e = hipEventSynchronize(b);
+      for (int k = 0; e == hipSuccess && k < 2 * nc; ++k) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, st->tune_ev[2 * k], st->tune_ev[2 * k + 1]);
+        best[k % nc] = std::min(best[k % nc], ms);
+      }
+      tune_events_free(st);
+      st->tune = 0;
+      if (e != hipSuccess) return ctx_hip(ctx, e, "pass-size timing");
+      const int i = (int)(std::min_element(best.begin(), best.end()) - best.begin());
+      st->chunk = st->tune_cand[i];
+      ctx->tuned_chunk[tune_key(st)] = st->chunk;
+    }
+    return TK_OK;
+  }
+  if (st->use_graph && st->warm && !ctx->prof && !st->plain) return state_step_graph(st);
+  return state_step_once(st);
+}
+
 tk_status state_moments_now(tk_state* st) {
   hipError_t e;
   if (st->plain) e = launch_plain_moments(plain_dev(st), st->mixed, st->ctx->stream);
@@ -646,7 +766,7 @@ tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait) {
                                     hipMemcpyDeviceToDevice, q);
       if (e != hipSuccess) return ctx_hip(ctx, e, "macro copy");
     }
-    if ((s = state_step_once(st)) != TK_OK) return s;
+    if ((s = state_step(st)) != TK_OK) return s;
   }
   if (!wait) return TK_OK;
   if ((s = state_moments_now(st)) != TK_OK) return s;
@@ -675,7 +795,7 @@ tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag) {
   hipError_t e = hipMemcpyAsync(st->d_macro_prev, st->d_macro, sizeof(double) * (size_t)st->nc * 8,
                                 hipMemcpyDeviceToDevice, q);
   if (e != hipSuccess) return ctx_hip(ctx, e, "macro copy");
-  if ((s = state_step_once(st)) != TK_OK) return s;
+  if ((s = state_step(st)) != TK_OK) return s;
   if ((s = state_moments_now(st)) != TK_OK) return s;
   e = launch_residual(st->d_macro_prev, st->d_macro, st->d_vol, st->d_inst_off, st->ninst, st->d_resid, q);
   if (e == hipSuccess) e = hipMemcpyAsync(h_res, st->d_resid, sizeof(double) * st->ninst, hipMemcpyDeviceToHost, q);
@@ -841,6 +961,49 @@ tk_status tk_state_info(const tk_state* st, int32_t* n_cells, int32_t* n_instanc
 tk_status tk_state_dt(const tk_state* st, int32_t inst, double* dt) {
   if (!st || !dt || inst < 0 || inst >= st->ninst) return TK_EINVAL;
   *dt = st->ip_host[inst].dt;
+  return TK_OK;
+}
+
+tk_status tk_state_set_chunk(tk_state* st, int32_t cells) {
+  if (!st) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(st->ctx->mu);
+  if (cells < 0 || cells > st->chunk_max)
+    return ctx_fail(st->ctx, TK_EINVAL, "pass size must be 0 (choose) or 1.." + std::to_string(st->chunk_max));
+  tune_events_free(st);
+  if (cells == 0) {
+    state_tune_begin(st);
+  } else {
+    st->tune = 0;
+    st->chunk = cells;
+  }
+  return TK_OK;
+}
+
+tk_status tk_state_chunk(const tk_state* st, int32_t* cells, int32_t* max_cells) {
+  if (!st) return TK_EINVAL;
+  if (cells) *cells = st->chunk;
+  if (max_cells) *max_cells = st->chunk_max;
+  return TK_OK;
+}
+
+tk_status tk_state_tune(tk_state* st, int32_t* steps_run) {
+  if (!st) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(st->ctx->mu);
+  int n = 0;
+  if (steps_run) *steps_run = 0;
+  while (st->tune == 1 && n < 64) {
+    const tk_status s = state_step(st);
+    if (s != TK_OK) return s;
+    ++n;
+    if (steps_run) *steps_run = n;
+  }
+  return ctx_hip(st->ctx, hipStreamSynchronize(st->ctx->stream), "tune sync");
+}
+
+tk_status tk_state_use_graph(tk_state* st, int32_t on) {
+  if (!st) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(st->ctx->mu);
+  st->use_graph = on != 0;
   return TK_OK;
 }
 

@@ -85,6 +85,9 @@ tk_status admit(tk_server* srv, ServeReq* r) {
   tk_status s = tk_ctx_create(srv->parent->device, r->bytes + (256u << 20), nullptr, &r->ctx);
   if (s == TK_OK) s = tk_mesh_load(r->ctx, &r->desc, &r->mesh);
   if (s == TK_OK) s = tk_state_init(r->ctx, r->mesh, &r->params, r->macro.data(), &r->st);
+  // one rounding pass per step (no pass-size trials: each request runs alone
+  // on its stream and its trial steps would serialise the mix)
+  if (s == TK_OK) s = tk_state_set_chunk(r->st, r->st->chunk_max);
   if (s == TK_OK && (hipHostMalloc((void**)&r->h_res, sizeof(double)) != hipSuccess ||
                      hipHostMalloc((void**)&r->h_flag, sizeof(int)) != hipSuccess))
     s = TK_EDEVICE;

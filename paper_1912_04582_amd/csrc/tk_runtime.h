@@ -25,6 +25,8 @@ struct tk_ctx {
   std::vector<hipEvent_t> ev_pool;
   double prof_ms[tk::KID_COUNT] = {};
   int64_t prof_n[tk::KID_COUNT] = {};
+  // rounding-pass sizes chosen by timing, per state shape
+  std::map<std::string, int> tuned_chunk;
 };
 
 struct tk_mesh {
@@ -50,7 +52,17 @@ struct tk_state {
   int N = 0, CS = 0;
   bool mixed = false, plain = false;
   int nc = 0, ninst = 0;
-  int chunk = 1;
+  int chunk = 1;      // cells per rounding pass in use
+  int chunk_max = 1;  // allocated
+  // pass-size tuning: 0 fixed, 1 tuning; the trial steps and their events
+  int tune = 0;
+  int tune_step = 0;
+  std::vector<int> tune_cand;
+  std::vector<hipEvent_t> tune_ev;
+  // graph replay of a step, one graph per buffer parity
+  bool use_graph = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int gchunk[2] = {0, 0};
   std::vector<tk_params> params;
   std::vector<const tk_mesh*> meshes;
   std::vector<int> inst_off;
@@ -104,4 +116,5 @@ void* ctx_alloc(tk_ctx* ctx, size_t bytes, tk_status* st);
 void ctx_free(tk_ctx* ctx, void* p);
 tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait);
 size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk);
+void state_tune_begin(tk_state* st);
 tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag);

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "TK_OK", 1: "TK_PENDING", -1: "TK_EINVAL", -2: "TK_ENOMEM", -
 EXPORTED = [
     "tk_ctx_create", "tk_ctx_destroy", "tk_last_error", "tk_sync", "tk_prof_enable", "tk_prof_get",
     "tk_prof_reset", "tk_prof_eig", "tk_mesh_load", "tk_mesh_destroy", "tk_state_init", "tk_state_init_batch",
-    "tk_state_destroy", "tk_state_info", "tk_state_dt", "tk_moments", "tk_step", "tk_step_async",
+    "tk_state_destroy", "tk_state_info", "tk_state_dt", "tk_state_set_chunk", "tk_state_chunk",
+    "tk_state_tune", "tk_state_use_graph", "tk_moments", "tk_step", "tk_step_async",
     "tk_state_ranks", "tk_state_export", "tk_round_tucker", "tk_plain_init", "tk_serve_create",
     "tk_serve_submit", "tk_serve_poll", "tk_serve_destroy",
 ]
@@ -100,6 +101,10 @@ def lib():
             "tk_state_destroy": [P],
             "tk_state_info": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
             "tk_state_dt": [P, C.c_int32, C.POINTER(C.c_double)],
+            "tk_state_set_chunk": [P, C.c_int32],
+            "tk_state_chunk": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+            "tk_state_tune": [P, C.POINTER(C.c_int32)],
+            "tk_state_use_graph": [P, C.c_int32],
             "tk_moments": [P, C.POINTER(C.c_double)],
             "tk_step": [P, C.c_int32, C.POINTER(C.c_double)],
             "tk_step_async": [P, C.c_int32],
@@ -286,6 +291,25 @@ class State:
         v = C.c_double()
         _check(lib().tk_state_dt(self.h, int(inst), C.byref(v)), self.ctx.h)
         return v.value
+
+    def set_chunk(self, cells):
+        """Cells per rounding pass; 0 = chosen by timing trial steps."""
+        _check(lib().tk_state_set_chunk(self.h, int(cells)), self.ctx.h)
+
+    def chunk(self):
+        c, m = C.c_int32(), C.c_int32()
+        _check(lib().tk_state_chunk(self.h, C.byref(c), C.byref(m)), self.ctx.h)
+        return c.value, m.value
+
+    def tune(self):
+        """Run the pass-size trial steps now (they advance the state);
+        returns how many were run."""
+        n = C.c_int32()
+        _check(lib().tk_state_tune(self.h, C.byref(n)), self.ctx.h)
+        return n.value
+
+    def use_graph(self, on=True):
+        _check(lib().tk_state_use_graph(self.h, 1 if on else 0), self.ctx.h)
 
     def moments(self):
         out = np.zeros((self.n_cells, 8))

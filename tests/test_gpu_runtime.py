@@ -1,0 +1,141 @@
+"""Runtime features on the GPU, through the C ABI: rounding-pass sizes,
+the pass-size choice by timed trial steps, graph replay of a step, and
+parity at the full sizes of the channel and jittered-box workloads on
+sampled cells (their dependency cones advanced by the FP64 oracle)."""
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import macro_rel_err
+from oracle import fv, tucker_dvm as td
+from paper_1912_04582_amd import tk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tk.Context(0)
+    yield c
+    c.close()
+
+
+def box_case(n=16, N=16, precision="fp64", cap=6, tol=1e-6):
+    cfg = dict(synth.make_config("cfg0"), N=N, cap=cap, tol=tol, precision=precision)
+    m = synth.periodic_box(n)
+    return m, cfg, synth.initial_macros(cfg, m)
+
+
+def test_pass_sizes_give_identical_bits(ctx):
+    m, cfg, m0 = box_case(8)
+    mesh = tk.Mesh(ctx, m)
+    a = tk.State(ctx, mesh, cfg, m0)
+    b = tk.State(ctx, mesh, cfg, m0)
+    _, cmax = a.chunk()
+    a.set_chunk(cmax)
+    b.set_chunk(37)  # 13 full passes and a ragged one of 31 cells
+    assert b.chunk() == (37, cmax)
+    a.step(3)
+    b.step(3)
+    assert np.array_equal(a.moments(), b.moments())
+    assert np.array_equal(a.ranks()[0], b.ranks()[0])
+    for c in (0, 100, 511):
+        ga, ua = a.export(c, cfg["N"])
+        gb, ub = b.export(c, cfg["N"])
+        assert np.array_equal(ga, gb) and all(np.array_equal(x, y) for x, y in zip(ua, ub))
+    with pytest.raises(tk.TkError) as ei:
+        b.set_chunk(cmax + 1)
+    assert ei.value.status == tk.TK_EINVAL
+    a.close(); b.close(); mesh.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_equals_eager(ctx, precision):
+    m, cfg, m0 = box_case(8, N=16, precision=precision)
+    mesh = tk.Mesh(ctx, m)
+    eager = tk.State(ctx, mesh, cfg, m0)
+    graph = tk.State(ctx, mesh, cfg, m0)
+    for s in (eager, graph):
+        s.set_chunk(200)
+    graph.use_graph(True)
+    # replays of both parities, eager work (moments) between them, and a
+    # pass-size change that forces a new capture
+    for k in range(5):
+        if k == 3:
+            eager.set_chunk(128)
+            graph.set_chunk(128)
+        eager.step(2)
+        graph.step(2)
+        ma, mb = eager.moments(), graph.moments()
+        assert np.array_equal(ma, mb), (k, np.abs(ma - mb).max())
+        assert np.array_equal(eager.ranks()[0], graph.ranks()[0])
+    eager.close(); graph.close(); mesh.close()
+
+
+def test_pass_size_choice_is_kept_per_shape():
+    c = tk.Context(0)
+    try:
+        m, cfg, m0 = box_case(16)  # 4096 cells: several candidate sizes
+        mesh = tk.Mesh(c, m)
+        a = tk.State(c, mesh, cfg, m0)
+        _, cmax = a.chunk()
+        trials = a.tune()
+        assert trials >= 4 and trials % 2 == 0
+        chosen, _ = a.chunk()
+        assert 256 <= chosen <= cmax
+        assert a.tune() == 0
+        # a second state of the same shape starts with the chosen size
+        b = tk.State(c, mesh, cfg, m0)
+        assert b.chunk()[0] == chosen
+        assert b.tune() == 0
+        # the trial steps computed the same bits as fixed-size steps
+        ref = tk.State(c, mesh, cfg, m0)
+        ref.set_chunk(cmax)
+        ref.step(trials)
+        assert np.array_equal(a.moments(), ref.moments())
+        for s in (a, b, ref):
+            s.close()
+        mesh.close()
+    finally:
+        c.close()
+
+
+def sampled_parity(name, steps, count, bar):
+    cfg = synth.make_config(name)
+    mesh = synth.configs.make_mesh(cfg)
+    m0 = synth.initial_macros(cfg, mesh)
+    fl, fr = mesh["face_left"], mesh["face_right"]
+    picks = []
+    for b in range(len(mesh["bc"])):
+        cand = fl[fr == -(b + 1)]
+        picks.append(int(cand[len(cand) // 3]))
+    rng = np.random.default_rng(5)
+    while len(picks) < count:
+        picks.append(int(rng.integers(mesh["n_cells"])))
+    picks = sorted(set(picks))
+    print(f"{name}: {mesh['n_cells']} cells, cells {picks}, {steps} steps", flush=True)
+    c = tk.Context(0)
+    try:
+        tm = tk.Mesh(c, mesh)
+        st = tk.State(c, tm, cfg, m0)
+        st.step(steps)
+        got = st.moments()[picks]
+        st.close()
+        tm.close()
+    finally:
+        c.close()
+    S = fv.Setup(mesh, cfg, m0)
+    ref = td.run_cone(S, m0, picks, steps)
+    ref = np.array([td.macros_of(S, ref[i]) for i in picks])
+    err, _ = macro_rel_err(got, ref)
+    print(f"{name}: max rel macro err {err:.3e} (bar {bar})")
+    assert err < bar, err
+
+
+def test_channel_full_size_sampled_cells():
+    sampled_parity("cfg1", 3, 8, 1e-5)
+
+
+def test_jittered_box_full_size_sampled_cells():
+    sampled_parity("cfg2", 2, 3, 1e-5)
