@@ -61,9 +61,17 @@ namespace {
 template <int NT, int NHMAX>
 __device__ void jacobi(double* A, int lda, double* V, int ldv, int nv, int n, double rel_thr, double abs_thr,
                        double* cs, double* sn, double* tt, int* pp, int* qq, int* flag, int* conv) {
+  // the (I, J) pair blocks of the update, tabulated once per call
+  __shared__ unsigned char b_i[NHMAX * (NHMAX + 1) / 2], b_j[NHMAX * (NHMAX + 1) / 2];
   const int lane = threadIdx.x;
   const int nh = n / 2;
   const int nblk = nh * (nh + 1) / 2;
+  for (int b = lane; b < nblk; b += NT) {
+    int I = 0, rem = b;
+    while (rem >= nh - I) { rem -= nh - I; ++I; }
+    b_i[b] = (unsigned char)I;
+    b_j[b] = (unsigned char)(I + rem);
+  }
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (lane == 0) {
       *conv = 1;
@@ -86,13 +94,19 @@ __device__ void jacobi(double* A, int lda, double* V, int ldv, int nv, int n, do
       // round's last barrier, or read a value that is already 0.
       const int f = r & 1;
       if (lane < nh) {
+        // round-robin pair of this lane in round r (no integer division:
+        // both indices wrap at most once)
         int p, q;
         if (lane == 0) {
           p = 0;
-          q = 1 + r % (n - 1);
+          q = 1 + r;
         } else {
-          p = 1 + (r + lane) % (n - 1);
-          q = 1 + (r + n - 1 - lane) % (n - 1);
+          int x = r + lane;
+          if (x >= n - 1) x -= n - 1;
+          int y = r + n - 1 - lane;
+          if (y >= n - 1) y -= n - 1;
+          p = 1 + x;
+          q = 1 + y;
         }
         if (p > q) { const int t = p; p = q; q = t; }
         const double app = A[p * lda + p], aqq = A[q * lda + q], apq = A[p * lda + q];
@@ -114,9 +128,7 @@ __device__ void jacobi(double* A, int lda, double* V, int ldv, int nv, int n, do
       __syncthreads();
       if (!flag[f]) continue;
       for (int b = lane; b < nblk; b += NT) {
-        int I = 0, rem = b;
-        while (rem >= nh - I) { rem -= nh - I; ++I; }
-        const int J = I + rem;
+        const int I = b_i[b], J = b_j[b];
         if (I == J) {
           const double t = tt[I];
           if (t != 0.0) {
@@ -204,7 +216,7 @@ __device__ inline int choose_rank(const double* lam, int stride, const int* orde
 }
 
 template <int N>
-__global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
+__global__ __launch_bounds__(kEigThreads, 5) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
                                                      int c0, double tol_o, int cap_o, int CS, double* fac_n,
                                                      int* rank_n, const double* Win, double* Wout, double* Wkeep,
                                                      double rel_thr, double abs_fac, double drop,
@@ -219,8 +231,8 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int
   __shared__ int pp[NH], qq[NH];
   __shared__ int order[N];
   __shared__ int flag[2], s_conv;
-  __shared__ double s_tot, s_aux;
-  __shared__ int s_rank, s_k, s_fast;
+  __shared__ double s_aux;
+  __shared__ int s_rank, s_fast;
   const int m = blockIdx.x;
   const int cl = m / 3, mode = m % 3;
   const int cell = c0 + cl;
@@ -234,31 +246,47 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int
     tol = P.tol;
     cap = P.cap;
   }
-  for (int o = lane; o < N * N; o += NT) {
-    const int i = o / N, j = o % N;
-    A[i * LD + j] = g[o];
-    // V[i][j]: entry i of vector j
-    V[i * LD + j] = wk ? wk[j * N + i] : ((i == j) ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  if (lane == 0) {
-    double t = 0.0;
-    for (int i = 0; i < N; ++i) t += A[i * LD + i];
-    s_tot = t;
-    s_fast = 0;
-    int k = N;
-    if (wk && lead > 0 && rank_prev) {
-      const int rp = rank_prev[3 * cell + mode];
-      k = (rp < 1 ? 1 : rp) + lead;
-      k += k & 1;
-      if (k > N) k = N;
+  // the matrix, the previous basis (V[i][j]: entry i of vector j) and the
+  // previous rank, all requested before any is used
+  const int rp = (wk && lead > 0 && rank_prev) ? rank_prev[3 * cell + mode] : 0;
+  {
+    constexpr int PER = (N * N + NT - 1) / NT;
+    double ga[PER], wa[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int o = lane + t * NT;
+      if (o < N * N) {
+        ga[t] = g[o];
+        wa[t] = wk ? wk[o] : (((o / N) == (o % N)) ? 1.0 : 0.0);
+      }
     }
-    s_k = k;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int o = lane + t * NT;
+      if (o < N * N) {
+        A[(o / N) * LD + o % N] = ga[t];
+        V[(o % N) * LD + o / N] = wa[t];
+      }
+    }
+  }
+  // leading block size (N: the full matrix)
+  int k = N;
+  if (wk && lead > 0 && rank_prev) {
+    k = (rp < 1 ? 1 : rp) + lead;
+    k += k & 1;
+    if (k > N) k = N;
   }
   __syncthreads();
-  const double thr = tol * tol * s_tot / 3.0;
-  const double abs_thr = abs_fac * fabs(s_tot);
-  const int k = s_k;
+  // trace, reduced by every wave
+  double tot = 0.0;
+  {
+    const int d = lane & 63;
+    if (d < N) tot = A[d * LD + d];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+  }
+  const double thr = tol * tol * tot / 3.0;
+  const double abs_thr = abs_fac * fabs(tot);
   if (k < N) {
     // ---- leading block of the previous basis: B = W_k^T G W_k -------------
     for (int o = lane; o < N * k; o += NT) {
@@ -280,7 +308,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(const double* Gm, const int
     if (lane == 0) {
       double tb = 0.0;
       for (int i = 0; i < k; ++i) tb += A[i * LD + i];
-      const double tail = s_tot - tb;
+      const double tail = tot - tb;
       s_aux = tail > 0.0 ? tail : 0.0;
       // the rest of the spectrum carries a negligible share of the trace
       s_fast = (drop == 0.0 && s_aux <= 1e-3 * thr) ? 1 : 0;

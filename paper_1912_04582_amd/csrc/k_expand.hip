@@ -27,44 +27,42 @@ namespace {
 
 constexpr int KC = 4;  // rank-1 chunk of the staged mode products
 
+// One source into the fibre accumulators: Y = G x3 U3 (all r1 x r2 x N in
+// LDS), then each thread forms z_j = sum_k2 U2[i2,k2] Y[j,k2,i3] for its own
+// fibres and adds U1[:,j] z_j.  One barrier between Y and its use; the
+// caller separates sources with a barrier before restaging.
 template <int N, int BLOCK, typename T, int FIB>
-__device__ inline void expand_source(T (&acc)[FIB][N], const T* sU, const T* sG, T* sY, T* sZ, int r1,
-                                     int r2, int r3, int CS, const int (&pf)[FIB]) {
+__device__ inline void expand_fibres(T (&acc)[FIB][N], const T* sU, const T* sG, T* sY, int r1, int r2, int r3,
+                                     int CS, const int (&pf)[FIB]) {
   const T* U1 = sU;
   const T* U2 = sU + CS * N;
   const T* U3 = sU + 2 * CS * N;
   const int tid = threadIdx.x;
-  for (int kb = 0; kb < r1; kb += KC) {
-    const int kc = min(KC, r1 - kb);
-    for (int o = tid; o < kc * r2 * N; o += BLOCK) {
-      const int i3 = o % N, t = o / N, k2 = t % r2, j = t / r2;
-      T s = 0;
-      const T* g = sG + (kb + j) + r1 * k2;
-      for (int k3 = 0; k3 < r3; ++k3) s += g[r1 * r2 * k3] * U3[k3 * N + i3];
-      sY[(j * r2 + k2) * N + i3] = s;
-    }
-    __syncthreads();
-    for (int o = tid; o < kc * N * N; o += BLOCK) {
-      const int i2 = o % N, t = o / N, i3 = t % N, j = t / N;
-      T s = 0;
+  for (int o = tid; o < r1 * r2 * N; o += BLOCK) {
+    const int i3 = o % N, t = o / N, k2 = t % r2, j = t / r2;
+    T sacc = 0;
+    const T* g = sG + j + r1 * k2;
+    for (int k3 = 0; k3 < r3; ++k3) sacc += g[r1 * r2 * k3] * U3[k3 * N + i3];
+    sY[o] = sacc;
+  }
+  __syncthreads();
+  for (int j = 0; j < r1; ++j) {
+    T z[FIB];
+#pragma unroll
+    for (int f = 0; f < FIB; ++f) {
+      const int i2 = pf[f] % N, i3 = pf[f] / N;
       const T* y = sY + j * r2 * N + i3;
-      for (int k2 = 0; k2 < r2; ++k2) s += U2[k2 * N + i2] * y[k2 * N];
-      sZ[o] = s;
+      T sacc = 0;
+      for (int k2 = 0; k2 < r2; ++k2) sacc += U2[k2 * N + i2] * y[k2 * N];
+      z[f] = sacc;
     }
-    __syncthreads();
-    for (int j = 0; j < kc; ++j) {
-      T z[FIB];
+    const T* u = U1 + j * N;
 #pragma unroll
-      for (int f = 0; f < FIB; ++f) z[f] = sZ[j * N * N + pf[f]];
-      const T* u = U1 + (kb + j) * N;
+    for (int i1 = 0; i1 < N; ++i1) {
+      const T uv = u[i1];
 #pragma unroll
-      for (int i1 = 0; i1 < N; ++i1) {
-        const T uv = u[i1];
-#pragma unroll
-        for (int f = 0; f < FIB; ++f) acc[f][i1] += uv * z[f];
-      }
+      for (int f = 0; f < FIB; ++f) acc[f][i1] += uv * z[f];
     }
-    __syncthreads();
   }
 }
 
@@ -103,8 +101,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
   T* sb = sd + 3 * N;             // N     row scaling of the current source
   T* sU = sb + N;                 // 3 CS N
   T* sG = sU + 3 * CS * N;        // CS^3
-  T* sY = sG + CS * CS * CS;      // KC CS N
-  T* sZ = sY + KC * CS * N;       // KC N N
+  T* sY = sG + CS * CS * CS;      // CS CS N
   const int c = c0 + blockIdx.x;
   const int tid = threadIdx.x;
   const InstParams P = d.ip[d.inst[c]];
@@ -135,7 +132,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
   for (int f = 0; f < FIB; ++f)
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[f][i] = 0;
-  expand_source<N, BLOCK, T, FIB>(acc, sU, sG, sY, sZ, r1, r2, r3, CS, pf);
+  expand_fibres<N, BLOCK, T, FIB>(acc, sU, sG, sY, r1, r2, r3, CS, pf);
+  __syncthreads();
   {
     const T cterm = (T)(1.0 - P.dt * nu);
 #pragma unroll
@@ -181,7 +179,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
       }
     }
     __syncthreads();
-    expand_source<N, BLOCK, T, FIB>(acc, sU, sG, sY, sZ, 4, 4, 4, CS, pf);
+    expand_fibres<N, BLOCK, T, FIB>(acc, sU, sG, sY, 4, 4, 4, CS, pf);
+    __syncthreads();
   }
 
   // far sides of the six faces
@@ -214,195 +213,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
       if (tid == 0) sG[0] = (T)gsc;
     }
     __syncthreads();
-    expand_source<N, BLOCK, T, FIB>(acc, sU, sG, sY, sZ, q1, q2, q3, CS, pf);
+    expand_fibres<N, BLOCK, T, FIB>(acc, sU, sG, sY, q1, q2, q3, CS, pf);
+    __syncthreads();
   }
 
-  T* out = X + (size_t)blockIdx.x * N * N * N;
-#pragma unroll
-  for (int f = 0; f < FIB; ++f)
-#pragma unroll
-    for (int i = 0; i < N; ++i) out[(size_t)pf[f] * N + i] = acc[f][i];
-}
-
-// Same update with every source staged into LDS in one pass (one global-load
-// latency per cell instead of one per source); used when the worst-case
-// staging area fits the LDS.  Source 0 is the cell, 1 is f_S, 2..7 the far
-// sides of the six face slots.
-constexpr int kSrc = 8;
-
-template <int N, int BLOCK, typename T>
-__global__ __launch_bounds__(BLOCK) void k_expand_pf(DevState d, int c0, T* X) {
-  constexpr int FIB = N * N / BLOCK;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
-  const int CS = d.CS;
-  T* sxi = smem;                     // N
-  T* sd = sxi + N;                   // 3 N
-  T* sY = sd + 3 * N;                // KC CS N
-  T* sZ = sY + KC * CS * N;          // KC N N
-  T* pool = sZ + KC * N * N;         // kSrc (3 CS N + CS^3)
-  __shared__ int s_r[kSrc][3];
-  __shared__ int s_offU[kSrc], s_offG[kSrc], s_on[kSrc];
-  const int c = c0 + blockIdx.x;
-  const int tid = threadIdx.x;
-  const InstParams P = d.ip[d.inst[c]];
-  const double nu = d.nu[c];
-  int pf[FIB];
-#pragma unroll
-  for (int f = 0; f < FIB; ++f) pf[f] = tid + BLOCK * f;
-  if (tid == 0) {
-    int off = 0;
-    for (int s = 0; s < kSrc; ++s) {
-      int r1 = 0, r2 = 0, r3 = 0, on = 1;
-      if (s == 0) {
-        r1 = d.rank[3 * c]; r2 = d.rank[3 * c + 1]; r3 = d.rank[3 * c + 2];
-      } else if (s == 1) {
-        r1 = r2 = r3 = 4;
-      } else {
-        const int l = s - 2;
-        const int8_t kind = d.slot_kind[kSlots * c + l];
-        if (kind == SK_NONE) {
-          on = 0;
-        } else if (kind == SK_INTERIOR || kind == SK_OUTFLOW || kind == SK_SYM) {
-          const int src = (kind == SK_INTERIOR) ? d.slot_nb[kSlots * c + l] : c;
-          r1 = d.rank[3 * src]; r2 = d.rank[3 * src + 1]; r3 = d.rank[3 * src + 2];
-        } else {
-          r1 = r2 = r3 = 1;
-        }
-      }
-      s_r[s][0] = r1; s_r[s][1] = r2; s_r[s][2] = r3; s_on[s] = on;
-      s_offU[s] = off;
-      off += 3 * CS * N;
-      s_offG[s] = off;
-      off += CS * CS * CS;
-    }
-  }
-  for (int i = tid; i < N; i += BLOCK) {
-    const double x = P.xi_min + i * P.dxi;
-    sxi[i] = (T)x;
-    for (int a = 0; a < 3; ++a) {
-      double sum = 0.0;
-      for (int l = 0; l < kSlots; ++l) {
-        const int8_t kind = d.slot_kind[kSlots * c + l];
-        if (kind == SK_NONE || d.slot_axis[kSlots * c + l] != a) continue;
-        sum -= d.slot_coef[kSlots * c + l] * fmax((double)d.slot_sig[kSlots * c + l] * x, 0.0);
-      }
-      sd[a * N + i] = (T)sum;
-    }
-  }
-  __syncthreads();
-  // ---- stage every source --------------------------------------------------
-  for (int s = 0; s < kSrc; ++s) {
-    if (!s_on[s]) continue;
-    T* sU = pool + s_offU[s];
-    T* sG = pool + s_offG[s];
-    const int r1 = s_r[s][0], r2 = s_r[s][1], r3 = s_r[s][2];
-    if (s == 1) {
-      // f_S in Tucker form, scaled by dt nu
-      const double* M = d.macro + 8 * (size_t)c;
-      const double n = M[0], T0 = M[4];
-      const double RT = P.Rg * T0;
-      const double amp = cbrt(n) / sqrt(2.0 * M_PI * RT);
-      const double beta = 1.0 / (2.0 * RT);
-      const double As = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * n * RT * RT);
-      for (int o = tid; o < 3 * N; o += BLOCK) {
-        const int a = o / N, i = o % N;
-        const double v = P.xi_min + i * P.dxi - M[1 + a];
-        const double base = amp * exp(-v * v * beta);
-        sU[a * CS * N + 0 * N + i] = (T)base;
-        sU[a * CS * N + 1 * N + i] = (T)(base * v);
-        sU[a * CS * N + 2 * N + i] = (T)(base * v * v);
-        sU[a * CS * N + 3 * N + i] = (T)(base * v * v * v);
-      }
-      if (tid < 64) {
-        // 4x4x4 core: 1, v_a, v_a^3 and v_a v_b^2 monomials
-        const int o = tid, k1 = o & 3, k2 = (o >> 2) & 3, k3 = o >> 4;
-        const int k[3] = {k1, k2, k3};
-        const double sc = P.dt * nu;
-        double g = 0.0;
-        int nz = 0, which = -1;
-        for (int a = 0; a < 3; ++a)
-          if (k[a]) { ++nz; which = a; }
-        if (nz == 0) {
-          g = 1.0;
-        } else if (nz == 1) {
-          const double qa = M[5 + which];
-          if (k[which] == 1) g = -2.5 * As * qa;
-          else if (k[which] == 3) g = As * beta * qa;
-        } else if (nz == 2) {
-          // v_a v_b^2 with a != b
-          for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b)
-              if (a != b && k[a] == 1 && k[b] == 2 && k[3 - a - b] == 0) g = As * beta * M[5 + a];
-        }
-        sG[o] = (T)(sc * g);
-      }
-      continue;
-    }
-    int src = c, rev = -1, ax = -1, bc = -1;
-    double coef = 0.0, sg = 0.0, gsc = 1.0;
-    if (s >= 2) {
-      const int l = s - 2;
-      const int8_t kind = d.slot_kind[kSlots * c + l];
-      ax = d.slot_axis[kSlots * c + l];
-      sg = (double)d.slot_sig[kSlots * c + l];
-      coef = d.slot_coef[kSlots * c + l];
-      const int nb = d.slot_nb[kSlots * c + l];
-      if (kind == SK_INTERIOR) src = nb;
-      if (kind == SK_SYM) rev = ax;
-      if (kind == SK_INFLOW || kind == SK_WALL) {
-        bc = nb;
-        if (kind == SK_WALL) gsc = d.nw[kSlots * c + l];
-      }
-    }
-    if (bc >= 0) {
-      const double* bf = d.bc_fac + (size_t)bc * 3 * N;
-      for (int o = tid; o < 3 * N; o += BLOCK) {
-        const int a = o / N, i = o % N;
-        double v = bf[o];
-        if (a == ax) v *= coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0);
-        sU[a * CS * N + i] = (T)v;
-      }
-      if (tid == 0) sG[0] = (T)gsc;
-      continue;
-    }
-    const int rr[3] = {r1, r2, r3};
-    for (int o = tid; o < 3 * CS * N; o += BLOCK) {
-      const int a = o / (CS * N), rem = o % (CS * N), k = rem / N, i = rem % N;
-      if (k >= rr[a]) continue;
-      const int is = (a == rev) ? (N - 1 - i) : i;
-      double v = d.fac[((size_t)src * 3 + a) * CS * N + k * N + is];
-      if (a == ax) v *= coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0);
-      sU[o] = (T)v;
-    }
-    for (int o = tid; o < r1 * r2 * r3; o += BLOCK) {
-      const int k1 = o % r1, t = o / r1, k2 = t % r2, k3 = t / r2;
-      sG[o] = (T)d.core[(size_t)src * CS * CS * CS + k1 + CS * (k2 + CS * k3)];
-    }
-  }
-  __syncthreads();
-  // ---- mode products, accumulated in registers --------------------------------
-  T acc[FIB][N];
-#pragma unroll
-  for (int f = 0; f < FIB; ++f)
-#pragma unroll
-    for (int i = 0; i < N; ++i) acc[f][i] = 0;
-  expand_source<N, BLOCK, T, FIB>(acc, pool + s_offU[0], pool + s_offG[0], sY, sZ, s_r[0][0], s_r[0][1],
-                                  s_r[0][2], CS, pf);
-  {
-    const T cterm = (T)(1.0 - P.dt * nu);
-#pragma unroll
-    for (int f = 0; f < FIB; ++f) {
-      const T dd = cterm + sd[N + pf[f] % N] + sd[2 * N + pf[f] / N];
-#pragma unroll
-      for (int i = 0; i < N; ++i) acc[f][i] *= (sd[i] + dd);
-    }
-  }
-  for (int s = 1; s < kSrc; ++s) {
-    if (!s_on[s]) continue;
-    expand_source<N, BLOCK, T, FIB>(acc, pool + s_offU[s], pool + s_offG[s], sY, sZ, s_r[s][0], s_r[s][1],
-                                    s_r[s][2], CS, pf);
-  }
   T* out = X + (size_t)blockIdx.x * N * N * N;
 #pragma unroll
   for (int f = 0; f < FIB; ++f)
@@ -686,8 +500,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand_plain(int CS, const double* co
   double* smem = reinterpret_cast<double*>(smem_raw);
   double* sU = smem;
   double* sG = sU + 3 * CS * N;
-  double* sY = sG + CS * CS * CS;
-  double* sZ = sY + KC * CS * N;
+  double* sY = sG + CS * CS * CS;  // CS CS N
   const int c = blockIdx.x;
   int pf[FIB];
 #pragma unroll
@@ -700,7 +513,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand_plain(int CS, const double* co
   for (int f = 0; f < FIB; ++f)
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[f][i] = 0;
-  expand_source<N, BLOCK, double, FIB>(acc, sU, sG, sY, sZ, r1, r2, r3, CS, pf);
+  expand_fibres<N, BLOCK, double, FIB>(acc, sU, sG, sY, r1, r2, r3, CS, pf);
   double* out = X + (size_t)c * N * N * N;
 #pragma unroll
   for (int f = 0; f < FIB; ++f)
@@ -719,16 +532,11 @@ template <int N, typename T>
 hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, hipStream_t s) {
   constexpr int B = ExpandShape<N>::B;
   const int CS = d.CS;
-  const size_t shp = sizeof(T) * (4 * N + KC * CS * N + KC * N * N + kSrc * (3 * CS * N + CS * CS * CS));
-  if (shp <= 120 * 1024) {
-    auto k = k_expand_pf<N, B, T>;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shp);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(count), dim3(B), shp, s, d, c0, (T*)X);
-    return hipGetLastError();
-  }
-  const size_t sh = sizeof(T) * (N + 3 * N + N + 3 * CS * N + CS * CS * CS + KC * CS * N + KC * N * N);
-  hipLaunchKernelGGL((k_expand<N, B, T>), dim3(count), dim3(B), sh, s, d, c0, (T*)X);
+  const size_t sh = sizeof(T) * (N + 3 * N + N + 3 * CS * N + CS * CS * CS + CS * CS * N);
+  auto k = k_expand<N, B, T>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(count), dim3(B), sh, s, d, c0, (T*)X);
   return hipGetLastError();
 }
 
@@ -773,13 +581,21 @@ hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixe
 hipError_t launch_expand_plain(int N, int count, int CS, const double* core, const double* fac,
                                const int* rank, double* X, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  const size_t sh = sizeof(double) * (3 * CS * N + CS * CS * CS + KC * CS * N + KC * N * N);
+  const size_t sh = sizeof(double) * (3 * CS * N + CS * CS * CS + CS * CS * N);
+#define TK_XP(NN, BB)                                                                                       \
+  do {                                                                                                      \
+    auto k = k_expand_plain<NN, BB>;                                                                        \
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh); \
+    if (e != hipSuccess) return e;                                                                          \
+    hipLaunchKernelGGL(k, dim3(count), dim3(BB), sh, s, CS, core, fac, rank, X);                            \
+  } while (0)
   switch (N) {
-    case 16: hipLaunchKernelGGL((k_expand_plain<16, 256>), dim3(count), dim3(256), sh, s, CS, core, fac, rank, X); break;
-    case 24: hipLaunchKernelGGL((k_expand_plain<24, 288>), dim3(count), dim3(288), sh, s, CS, core, fac, rank, X); break;
-    case 32: hipLaunchKernelGGL((k_expand_plain<32, 512>), dim3(count), dim3(512), sh, s, CS, core, fac, rank, X); break;
+    case 16: TK_XP(16, 256); break;
+    case 24: TK_XP(24, 288); break;
+    case 32: TK_XP(32, 512); break;
     default: return hipErrorInvalidValue;
   }
+#undef TK_XP
   return hipGetLastError();
 }
 
