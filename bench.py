@@ -296,13 +296,16 @@ def serve_run(reqs, rate, seed=5):
             while time.perf_counter() - t0 < t_next:
                 time.sleep(0.001)
         tickets.append(srv.submit(m, c, m0, steps, rtol))
+        log(f"    submitted request {len(tickets) - 1} at {time.perf_counter() - t0:.2f} s")
     done = {}
     while len(done) < len(tickets):
-        for t in tickets:
+        for i, t in enumerate(tickets):
             if t not in done:
                 r = srv.poll(t, want_macros=False)
                 if r["status"] != tk.TK_PENDING:
                     done[t] = r
+                    log(f"    request {i}: {reqs[i][0]['n_cells']} cells, {r['steps']} steps, "
+                        f"latency {r['t_done'] - r['t_arrive']:.2f} s ({len(done)}/{len(tickets)} done)")
         time.sleep(0.002)
     t1 = time.perf_counter()
     srv.close()
@@ -315,6 +318,7 @@ def serve_run(reqs, rate, seed=5):
 
 
 def run_serve(count, max_steps, seed=4):
+    log(f"serving {count} requests: saturated, then Poisson at 0.7x and 0.35x the saturated rate")
     specs = synth.configs.serve_requests(seed=seed, count=count)
     reqs = []
     for c in specs:

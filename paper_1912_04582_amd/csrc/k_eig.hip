@@ -216,7 +216,7 @@ __device__ inline int choose_rank(const double* lam, int stride, const int* orde
 }
 
 template <int N>
-__global__ __launch_bounds__(kEigThreads, 5) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
+__global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
                                                      int c0, double tol_o, int cap_o, int CS, double* fac_n,
                                                      int* rank_n, const double* Win, double* Wout, double* Wkeep,
                                                      double rel_thr, double abs_fac, double drop,
