@@ -294,26 +294,253 @@ __device__ inline void stage_any(const double* core, const double* fac, int CSsr
   }
 }
 
+
+// ---- fast path: every source staged once per cell ---------------------------
+// Sources: the cell, f_S, and per face slot the far side (state or ghost)
+// followed, on an oblique face, by its |xi.e| estimate.  Each is kept in LDS
+// as its mode-1 and mode-2 factors and Y = G x3 U3 (r1 x r2 x N); G and U3
+// pass through a scratch area source by source.  The fibre passes then need
+// no barrier: per fibre and per half of mode 1 a thread expands the cell,
+// f_S, each far side and each estimate into registers and combines them
+// node by node.
+constexpr int kObSrcMax = 2 + 2 * kSlots;
+enum ObRole : int { OB_OWN = 0, OB_FS = 1, OB_FAR_AXIS = 2, OB_FAR_OBL = 3, OB_EST = 4 };
+
+struct ObTab {
+  int n;
+  int role[kObSrcMax], slot[kObSrcMax];
+  int r[kObSrcMax][3];
+  int offU[kObSrcMax], offY[kObSrcMax];
+  int tmp;   // offset of the scratch area (G and U3 of one source)
+  int need;  // floats in use from the start of the source area
+};
+
+// Halves of mode 1 a thread expands at once: at most 96 bytes of fibre per
+// register array.
+template <int N, typename T>
+constexpr int ob_halves() {
+  int h = 1;
+  while ((N * (int)sizeof(T)) / h > 96 || N % h) ++h;
+  return h;
+}
+
+// Expand source s of the table over nodes [i0, i0 + NH) of fibre (i2, i3),
+// adding into out.
+template <int N, int NH, typename T>
+__device__ inline void ob_fibre(const ObTab& tb, int s, const T* src, int i2, int i3, int i0, T (&out)[NH]) {
+  const int r1 = tb.r[s][0], r2 = tb.r[s][1];
+  const T* U1 = src + tb.offU[s];
+  const T* U2 = U1 + r1 * N;
+  const T* Y = src + tb.offY[s];
+  for (int j = 0; j < r1; ++j) {
+    T z = 0;
+    const T* y = Y + j * r2 * N + i3;
+    for (int k2 = 0; k2 < r2; ++k2) z += U2[k2 * N + i2] * y[k2 * N];
+    const T* u = U1 + j * N + i0;
+#pragma unroll
+    for (int i = 0; i < NH; ++i) out[i] += u[i] * z;
+  }
+}
+
 template <int N, int BLOCK, typename T>
-__global__ __launch_bounds__(BLOCK) void k_expand_obl(DevState d, int c0, T* X) {
+__device__ void ob_fast(const DevState& d, int c, T* Xc, const T* sxi, const T* sd, T* src, const ObTab& tb,
+                        const double (&nrm)[kSlots][3]) {
   constexpr int NPASS = N * N / BLOCK;
-  static_assert(NPASS * BLOCK == N * N, "passes must tile the fibres");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
-  const int CS = d.CS;
-  const int CSL = CS > kEstCap ? CS : kEstCap;
-  T* sxi = smem;                  // N
-  T* sd = sxi + N;                // 3 N   separable (axis-aligned) outflow tables
-  T* sU = sd + 3 * N;             // 3 CSL N
-  T* sG = sU + 3 * CSL * N;       // CSL^3
-  T* sY = sG + CSL * CSL * CSL;   // KC CSL N
-  T* sZ = sY + KC * CSL * N;      // KC BLOCK
-  __shared__ double s_nrm[kSlots][3];
-  const int c = c0 + blockIdx.x;
+  constexpr int H = ob_halves<N, T>();
+  constexpr int NH = N / H;
   const int tid = threadIdx.x;
   const InstParams P = d.ip[d.inst[c]];
   const double nu = d.nu[c];
-  if (tid < kSlots * 3) s_nrm[tid / 3][tid % 3] = d.slot_nrm[(size_t)kSlots * 3 * c + tid];
+  const double* M = d.macro + 8 * (size_t)c;
+  const int CS = d.CS;
+  // ---- staging, source by source: U1, U2 to their slots, G and U3 to the
+  // scratch area, then Y = G x3 U3
+  for (int s = 0; s < tb.n; ++s) {
+    const int role = tb.role[s], l = tb.slot[s];
+    const int r1 = tb.r[s][0], r2 = tb.r[s][1], r3 = tb.r[s][2];
+    T* U = src + tb.offU[s];        // U1 (r1 N), U2 (r2 N)
+    T* G = src + tb.tmp;            // r1 r2 r3
+    T* U3 = G + r1 * r2 * r3;       // r3 N
+    const int nU = (r1 + r2 + r3) * N;
+    int kind = 0, ax = -1, nb = 0;
+    double coef = 0.0, sg = 0.0, gsc = 1.0;
+    if (role == OB_FAR_AXIS || role == OB_FAR_OBL || role == OB_EST) {
+      kind = d.slot_kind[kSlots * c + l];
+      ax = d.slot_axis[kSlots * c + l];
+      nb = d.slot_nb[kSlots * c + l];
+      coef = d.slot_coef[kSlots * c + l];
+      sg = (double)d.slot_sig[kSlots * c + l];
+      if (kind == SK_WALL) gsc = d.nw[kSlots * c + l];
+    }
+    // f_S parameters
+    const double n0 = M[0], T0 = M[4];
+    const double RT = P.Rg * T0;
+    const double amp = cbrt(n0) / sqrt(2.0 * M_PI * RT);
+    const double beta = 1.0 / (2.0 * RT);
+    const double As = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * n0 * RT * RT);
+    for (int o = tid; o < nU; o += BLOCK) {
+      int a, k, i;
+      if (o < r1 * N) { a = 0; k = o / N; i = o % N; }
+      else if (o < (r1 + r2) * N) { a = 1; k = (o - r1 * N) / N; i = o % N; }
+      else { a = 2; k = (o - (r1 + r2) * N) / N; i = o % N; }
+      double v;
+      if (role == OB_OWN) {
+        v = d.fac[((size_t)c * 3 + a) * CS * N + (size_t)k * N + i];
+      } else if (role == OB_FS) {
+        const double x = P.xi_min + i * P.dxi - M[1 + a];
+        v = amp * exp(-x * x * beta);
+        for (int q = 0; q < k; ++q) v *= x;
+      } else if (role == OB_EST) {
+        const int e = d.slot_est[kSlots * c + l];
+        v = d.est_fac[(((size_t)e * 3 + a) * kEstCap + k) * N + i];
+      } else if (kind == SK_INTERIOR || kind == SK_OUTFLOW || kind == SK_SYM) {
+        const int sc = (kind == SK_INTERIOR) ? nb : c;
+        const int is = (kind == SK_SYM && a == ax) ? (N - 1 - i) : i;
+        v = d.fac[((size_t)sc * 3 + a) * CS * N + (size_t)k * N + is];
+        if (role == OB_FAR_AXIS && a == ax) v *= coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0);
+      } else {
+        v = d.bc_fac[((size_t)nb * 3 + a) * N + i];
+        if (role == OB_FAR_AXIS && a == ax) v *= coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0);
+      }
+      if (a < 2) U[o] = (T)v;
+      else U3[o - (r1 + r2) * N] = (T)v;
+    }
+    for (int o = tid; o < r1 * r2 * r3; o += BLOCK) {
+      const int k1 = o % r1, t = o / r1, k2 = t % r2, k3 = t / r2;
+      double g;
+      if (role == OB_OWN) {
+        g = d.core[(size_t)c * CS * CS * CS + k1 + CS * (k2 + CS * k3)];
+      } else if (role == OB_FS) {
+        // 13 non-zeros of the f_S core (Proposition 1), times dt nu
+        const int kk[3] = {k1, k2, k3};
+        int nz = 0, which = -1;
+        for (int a = 0; a < 3; ++a)
+          if (kk[a]) { ++nz; which = a; }
+        g = 0.0;
+        if (nz == 0) {
+          g = 1.0;
+        } else if (nz == 1) {
+          if (kk[which] == 1) g = -2.5 * As * M[5 + which];
+          else if (kk[which] == 3) g = As * beta * M[5 + which];
+        } else if (nz == 2) {
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+              if (a != b && kk[a] == 1 && kk[b] == 2 && kk[3 - a - b] == 0) g = As * beta * M[5 + a];
+        }
+        g *= P.dt * nu;
+      } else if (role == OB_EST) {
+        const int e = d.slot_est[kSlots * c + l];
+        g = d.est_core[(size_t)e * kEstCap * kEstCap * kEstCap + k1 + kEstCap * (k2 + kEstCap * k3)];
+      } else if (kind == SK_INTERIOR || kind == SK_OUTFLOW || kind == SK_SYM) {
+        const int sc = (kind == SK_INTERIOR) ? nb : c;
+        g = d.core[(size_t)sc * CS * CS * CS + k1 + CS * (k2 + CS * k3)];
+      } else {
+        g = gsc;
+      }
+      G[o] = (T)g;
+    }
+    __syncthreads();
+    T* Y = src + tb.offY[s];
+    for (int o = tid; o < r1 * r2 * N; o += BLOCK) {
+      const int i3 = o % N, t = o / N, k2 = t % r2, j = t / r2;
+      T acc = 0;
+      const T* g = G + j + r1 * k2;
+      for (int k3 = 0; k3 < r3; ++k3) acc += g[r1 * r2 * k3] * U3[k3 * N + i3];
+      Y[o] = acc;
+    }
+    __syncthreads();
+  }
+  // ---- fibre passes
+  const T c1 = (T)(1.0 - P.dt * nu);
+  for (int pass = 0; pass < NPASS; ++pass) {
+    const int p = pass * BLOCK + tid;
+    const int i2 = p % N, i3 = p / N;
+    const T base = c1 + sd[N + i2] + sd[2 * N + i3];
+    T* out = Xc + (size_t)p * N;
+    for (int h = 0; h < H; ++h) {
+      const int i0 = h * NH;
+      T own[NH], acc[NH];
+#pragma unroll
+      for (int i = 0; i < NH; ++i) own[i] = 0;
+      ob_fibre<N, NH, T>(tb, 0, src, i2, i3, i0, own);
+#pragma unroll
+      for (int i = 0; i < NH; ++i) acc[i] = (base + sd[i0 + i]) * own[i];
+      ob_fibre<N, NH, T>(tb, 1, src, i2, i3, i0, acc);
+      for (int s = 2; s < tb.n; ++s) {
+        const int role = tb.role[s];
+        if (role == OB_FAR_AXIS) {
+          ob_fibre<N, NH, T>(tb, s, src, i2, i3, i0, acc);
+        } else if (role == OB_FAR_OBL) {
+          // W gains a_l (xi_n + est), the far side is weighted by
+          // a_l (xi_n - est): acc += a_l (xi_n (own + g) + est (own - g))
+          const int l = tb.slot[s];
+          T g[NH], e[NH];
+#pragma unroll
+          for (int i = 0; i < NH; ++i) { g[i] = 0; e[i] = 0; }
+          ob_fibre<N, NH, T>(tb, s, src, i2, i3, i0, g);
+          ob_fibre<N, NH, T>(tb, s + 1, src, i2, i3, i0, e);
+          const T al = (T)(-0.5 * d.slot_coef[kSlots * c + l]);
+          const T n1 = (T)nrm[l][0];
+          const T x23 = (T)(nrm[l][1] * (double)sxi[i2] + nrm[l][2] * (double)sxi[i3]);
+#pragma unroll
+          for (int i = 0; i < NH; ++i) {
+            const T xn = n1 * sxi[i0 + i] + x23;
+            acc[i] += al * (xn * (own[i] + g[i]) + e[i] * (own[i] - g[i]));
+          }
+          ++s;  // the estimate was consumed with its face
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NH; ++i) out[i0 + i] = acc[i];
+    }
+  }
+}
+
+// Source table of cell c and the floats it needs after the tables; built by
+// one thread.
+__device__ inline void ob_table(const DevState& d, int c, int N, ObTab& tb) {
+  int off = 0, n = 0, tmp = 0;
+  auto add = [&](int role, int slot, int r1, int r2, int r3) {
+    tb.role[n] = role;
+    tb.slot[n] = slot;
+    tb.r[n][0] = r1; tb.r[n][1] = r2; tb.r[n][2] = r3;
+    tb.offU[n] = off;
+    off += (r1 + r2) * N;
+    tb.offY[n] = off;
+    off += r1 * r2 * N;
+    const int t = r1 * r2 * r3 + r3 * N;
+    if (t > tmp) tmp = t;
+    ++n;
+  };
+  add(OB_OWN, -1, d.rank[3 * c], d.rank[3 * c + 1], d.rank[3 * c + 2]);
+  add(OB_FS, -1, 4, 4, 4);
+  for (int l = 0; l < kSlots; ++l) {
+    const int kind = d.slot_kind[kSlots * c + l];
+    if (kind == SK_NONE) continue;
+    const bool obl = d.slot_axis[kSlots * c + l] < 0;
+    int q[3] = {1, 1, 1};
+    if (kind == SK_INTERIOR || kind == SK_OUTFLOW || kind == SK_SYM) {
+      const int sc = (kind == SK_INTERIOR) ? d.slot_nb[kSlots * c + l] : c;
+      for (int a = 0; a < 3; ++a) q[a] = d.rank[3 * sc + a];
+    }
+    add(obl ? OB_FAR_OBL : OB_FAR_AXIS, l, q[0], q[1], q[2]);
+    if (obl) {
+      const int e = d.slot_est[kSlots * c + l];
+      add(OB_EST, l, d.est_rank[3 * e], d.est_rank[3 * e + 1], d.est_rank[3 * e + 2]);
+    }
+  }
+  tb.n = n;
+  tb.tmp = off;
+  tb.need = off + tmp;
+}
+
+// Per-cell tables of both paths: the velocity nodes, the separable
+// (axis-aligned) outflow tables and the outward normals of the face slots.
+template <int N, int BLOCK, typename T>
+__device__ inline void ob_tables(const DevState& d, int c, T* sxi, T* sd, double (&nrm)[kSlots][3]) {
+  const int tid = threadIdx.x;
+  const InstParams P = d.ip[d.inst[c]];
+  if (tid < kSlots * 3) nrm[tid / 3][tid % 3] = d.slot_nrm[(size_t)kSlots * 3 * c + tid];
   for (int i = tid; i < N; i += BLOCK) {
     const double x = P.xi_min + i * P.dxi;
     sxi[i] = (T)x;
@@ -327,6 +554,26 @@ __global__ __launch_bounds__(BLOCK) void k_expand_obl(DevState d, int c0, T* X) 
       sd[a * N + i] = (T)sum;
     }
   }
+}
+
+// General path (any ranks): sources restaged for every pass of fibres.
+template <int N, int BLOCK, typename T>
+__device__ void ob_slow(const DevState& d, const int c, T* Xc, T* smem) {
+  constexpr int NPASS = N * N / BLOCK;
+  static_assert(NPASS * BLOCK == N * N, "passes must tile the fibres");
+  const int CS = d.CS;
+  const int CSL = CS > kEstCap ? CS : kEstCap;
+  T* sxi = smem;                  // N
+  T* sd = sxi + N;                // 3 N   separable (axis-aligned) outflow tables
+  T* sU = sd + 3 * N;             // 3 CSL N
+  T* sG = sU + 3 * CSL * N;       // CSL^3
+  T* sY = sG + CSL * CSL * CSL;   // KC CSL N
+  T* sZ = sY + KC * CSL * N;      // KC BLOCK
+  __shared__ double s_nrm[kSlots][3];
+  const int tid = threadIdx.x;
+  const InstParams P = d.ip[d.inst[c]];
+  const double nu = d.nu[c];
+  ob_tables<N, BLOCK, T>(d, c, sxi, sd, s_nrm);
   __syncthreads();
   const double* M = d.macro + 8 * (size_t)c;
   for (int pass = 0; pass < NPASS; ++pass) {
@@ -466,11 +713,48 @@ __global__ __launch_bounds__(BLOCK) void k_expand_obl(DevState d, int c0, T* X) 
         for (int i = 0; i < N; ++i) acc[i] += tmp[i] * w[i];
       }
     }
-    T* out = X + (size_t)blockIdx.x * N * N * N + (size_t)p * N;
+    T* out = Xc + (size_t)p * N;
 #pragma unroll
     for (int i = 0; i < N; ++i) out[i] = acc[i];
   }
 }
+
+// Cells whose sources fit the LDS budget take the one-stage path; the others
+// are listed for k_expand_obl_general.
+template <int N, int BLOCK, typename T>
+__global__ __launch_bounds__(BLOCK) void k_expand_obl(DevState d, int c0, T* X, int lds_floats, int* list,
+                                                      int* list_n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  T* sxi = smem;      // N
+  T* sd = sxi + N;    // 3 N
+  __shared__ double s_nrm[kSlots][3];
+  __shared__ ObTab s_tab;
+  const int c = c0 + blockIdx.x;
+  ob_tables<N, BLOCK, T>(d, c, sxi, sd, s_nrm);
+  if (threadIdx.x == 0) ob_table(d, c, N, s_tab);
+  __syncthreads();
+  if (s_tab.need > lds_floats - 4 * N) {
+    if (threadIdx.x == 0) list[atomicAdd(list_n, 1)] = blockIdx.x;
+    return;
+  }
+  ob_fast<N, BLOCK, T>(d, c, X + (size_t)blockIdx.x * N * N * N, sxi, sd, sd + 3 * N, s_tab, s_nrm);
+}
+
+template <int N, int BLOCK, typename T>
+__global__ __launch_bounds__(BLOCK) void k_expand_obl_general(DevState d, int c0, T* X, const int* list,
+                                                              const int* list_n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int n = *list_n;
+  for (int b = blockIdx.x; b < n; b += gridDim.x) {
+    const int bi = list[b];
+    ob_slow<N, BLOCK, T>(d, c0 + bi, X + (size_t)bi * N * N * N, smem);
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_count(int* p) { *p = 0; }
 
 template <int N>
 struct OblShape;
@@ -480,14 +764,23 @@ template <> struct OblShape<32> { static constexpr int B = 512; };
 template <> struct OblShape<48> { static constexpr int B = 384; };
 
 template <int N, typename T>
-hipError_t launch_expand_obl_t(const DevState& d, int c0, int count, void* X, hipStream_t s) {
+hipError_t launch_expand_obl_t(const DevState& d, int c0, int count, void* X, int* list, int* list_n,
+                               hipStream_t s) {
   constexpr int B = OblShape<N>::B;
-  const int CSL = d.CS > kEstCap ? d.CS : kEstCap;
-  const size_t sh = sizeof(T) * (4 * N + 3 * CSL * N + CSL * CSL * CSL + KC * CSL * N + KC * B);
-  auto k = k_expand_obl<N, B, T>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  // one-stage path of low-rank cells: two workgroups per CU
+  const size_t fast = (size_t)76 * 1024;
+  auto kf = k_expand_obl<N, B, T>;
+  hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fast);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(count), dim3(B), sh, s, d, c0, (T*)X);
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, list_n);
+  hipLaunchKernelGGL(kf, dim3(count), dim3(B), fast, s, d, c0, (T*)X, (int)(fast / sizeof(T)), list, list_n);
+  // the listed cells, any ranks
+  const int CSL = d.CS > kEstCap ? d.CS : kEstCap;
+  const size_t slow = sizeof(T) * (4 * N + 3 * CSL * N + CSL * CSL * CSL + KC * CSL * N + KC * B);
+  auto ks = k_expand_obl_general<N, B, T>;
+  e = hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)slow);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ks, dim3(count < 1024 ? count : 1024), dim3(B), slow, s, d, c0, (T*)X, list, list_n);
   return hipGetLastError();
 }
 
@@ -542,21 +835,22 @@ hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, hipStr
 
 }  // namespace
 
-hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixed, int oblique, hipStream_t s) {
+hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixed, int oblique, int* list,
+                         int* list_n, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (oblique) {
     if (mixed) {
       switch (d.N) {
-        case 16: return launch_expand_obl_t<16, float>(d, c0, count, X, s);
-        case 24: return launch_expand_obl_t<24, float>(d, c0, count, X, s);
-        case 32: return launch_expand_obl_t<32, float>(d, c0, count, X, s);
-        case 48: return launch_expand_obl_t<48, float>(d, c0, count, X, s);
+        case 16: return launch_expand_obl_t<16, float>(d, c0, count, X, list, list_n, s);
+        case 24: return launch_expand_obl_t<24, float>(d, c0, count, X, list, list_n, s);
+        case 32: return launch_expand_obl_t<32, float>(d, c0, count, X, list, list_n, s);
+        case 48: return launch_expand_obl_t<48, float>(d, c0, count, X, list, list_n, s);
       }
     } else {
       switch (d.N) {
-        case 16: return launch_expand_obl_t<16, double>(d, c0, count, X, s);
-        case 24: return launch_expand_obl_t<24, double>(d, c0, count, X, s);
-        case 32: return launch_expand_obl_t<32, double>(d, c0, count, X, s);
+        case 16: return launch_expand_obl_t<16, double>(d, c0, count, X, list, list_n, s);
+        case 24: return launch_expand_obl_t<24, double>(d, c0, count, X, list, list_n, s);
+        case 32: return launch_expand_obl_t<32, double>(d, c0, count, X, list, list_n, s);
       }
     }
     return hipErrorInvalidValue;

@@ -492,6 +492,10 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     S->X = st_alloc(S, per * 0 + (size_t)S->chunk * N * N * N * tsz, &s);
     if (!S->X) { state_free(S); return s; }
     ALLOC(G, double, (size_t)S->chunk * 3 * N * N);
+    if (oblique) {
+      ALLOC(ob_list, int, (size_t)S->chunk);
+      ALLOC(ob_n, int, 1);
+    }
     if (!S->mixed) ALLOC(Wb, double, (size_t)S->chunk * 3 * N * N);
     ALLOC(Wkeep, double, (size_t)nc * 3 * N * N);
   }
@@ -644,7 +648,7 @@ static tk_status state_step_once(tk_state* st) {
   for (int c0 = 0; c0 < st->nc; c0 += st->chunk) {
     const int cnt = std::min(st->chunk, st->nc - c0);
     prof_begin(ctx, KID_EXPAND, &ev);
-    e = launch_expand(d, c0, cnt, st->X, st->mixed, st->oblique ? 1 : 0, q);
+    e = launch_expand(d, c0, cnt, st->X, st->mixed, st->oblique ? 1 : 0, st->ob_list, st->ob_n, q);
     prof_end(ctx, KID_EXPAND, ev);
     if (e != hipSuccess) return ctx_hip(ctx, e, "expand");
     prof_begin(ctx, KID_GRAM, &ev);

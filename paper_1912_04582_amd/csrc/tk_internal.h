@@ -80,7 +80,10 @@ extern const char* kKernelNames[KID_COUNT];
 // ---- launchers (each enqueues on `s`) -------------------------------------
 hipError_t launch_init_maxwell(const DevState& d, const double* macro5, hipStream_t s);
 hipError_t launch_moments(const DevState& d, hipStream_t s);
-hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixed, int oblique, hipStream_t s);
+// oblique: list/list_n hold the cells of the pass left to the general path
+// (device memory for `count` cells and a counter)
+hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixed, int oblique, int* list,
+                         int* list_n, hipStream_t s);
 hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hipStream_t s);
 // eig of Grams [count][3][N][N]; writes factors/ranks of cells c0.. into the
 // next buffers (tol/cap per instance via inst/ip, or the overrides when
