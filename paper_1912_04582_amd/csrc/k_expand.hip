@@ -102,6 +102,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
   T* sU = sb + N;                 // 3 CS N
   T* sG = sU + 3 * CS * N;        // CS^3
   T* sY = sG + CS * CS * CS;      // CS CS N
+  T* sFU = sY + CS * CS * N;      // 3 CS N   f_S factors
+  T* sFG = sFU + 3 * CS * N;      // 64       f_S core
   const int c = c0 + blockIdx.x;
   const int tid = threadIdx.x;
   const InstParams P = d.ip[d.inst[c]];
@@ -121,6 +123,41 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
         s -= d.slot_coef[kSlots * c + l] * fmax((double)d.slot_sig[kSlots * c + l] * x, 0.0);
       }
       sd[a * N + i] = (T)s;
+    }
+  }
+  // f_S in Tucker form, scaled by dt nu, staged before the accumulators are
+  // live (its FP64 set-up would otherwise share their registers)
+  {
+    const double* M = d.macro + 8 * (size_t)c;
+    const double n = M[0], T0 = M[4];
+    const double RT = P.Rg * T0;
+    const double amp = cbrt(n) / sqrt(2.0 * M_PI * RT);
+    const double beta = 1.0 / (2.0 * RT);
+    const double As = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * n * RT * RT);
+    for (int o = tid; o < 3 * N; o += BLOCK) {
+      const int a = o / N, i = o % N;
+      const double v = P.xi_min + i * P.dxi - M[1 + a];
+      const double base = amp * exp(-v * v * beta);
+      sFU[a * CS * N + 0 * N + i] = (T)base;
+      sFU[a * CS * N + 1 * N + i] = (T)(base * v);
+      sFU[a * CS * N + 2 * N + i] = (T)(base * v * v);
+      sFU[a * CS * N + 3 * N + i] = (T)(base * v * v * v);
+    }
+    if (tid == 0) {
+      for (int o = 0; o < 64; ++o) sFG[o] = 0;
+      const double sc = P.dt * nu;
+      sFG[0] = (T)sc;
+      for (int a = 0; a < 3; ++a) {
+        const double qa = M[5 + a];
+        int st = (a == 0) ? 1 : (a == 1 ? 4 : 16);
+        sFG[1 * st] += (T)(sc * -2.5 * As * qa);
+        sFG[3 * st] += (T)(sc * As * beta * qa);
+        for (int b2 = 0; b2 < 3; ++b2) {
+          if (b2 == a) continue;
+          const int sb2 = (b2 == 0) ? 1 : (b2 == 1 ? 4 : 16);
+          sFG[1 * st + 2 * sb2] += (T)(sc * As * beta * qa);
+        }
+      }
     }
   }
   const int r1 = d.rank[3 * c], r2 = d.rank[3 * c + 1], r3 = d.rank[3 * c + 2];
@@ -143,45 +180,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
       for (int i = 0; i < N; ++i) acc[f][i] *= (sd[i] + dd);
     }
   }
-
-  // f_S in Tucker form, scaled by dt nu
-  {
-    const double* M = d.macro + 8 * (size_t)c;
-    const double n = M[0], T0 = M[4];
-    const double RT = P.Rg * T0;
-    const double amp = cbrt(n) / sqrt(2.0 * M_PI * RT);
-    const double beta = 1.0 / (2.0 * RT);
-    const double As = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * n * RT * RT);
-    for (int o = tid; o < 3 * N; o += BLOCK) {
-      const int a = o / N, i = o % N;
-      const double v = P.xi_min + i * P.dxi - M[1 + a];
-      const double base = amp * exp(-v * v * beta);
-      sU[a * CS * N + 0 * N + i] = (T)base;
-      sU[a * CS * N + 1 * N + i] = (T)(base * v);
-      sU[a * CS * N + 2 * N + i] = (T)(base * v * v);
-      sU[a * CS * N + 3 * N + i] = (T)(base * v * v * v);
-    }
-    for (int o = tid; o < 64; o += BLOCK) sG[o] = 0;
-    __syncthreads();
-    if (tid == 0) {
-      const double s = P.dt * nu;
-      sG[0] = (T)s;
-      for (int a = 0; a < 3; ++a) {
-        const double qa = M[5 + a];
-        int st = (a == 0) ? 1 : (a == 1 ? 4 : 16);
-        sG[1 * st] += (T)(s * -2.5 * As * qa);
-        sG[3 * st] += (T)(s * As * beta * qa);
-        for (int b = 0; b < 3; ++b) {
-          if (b == a) continue;
-          const int sb2 = (b == 0) ? 1 : (b == 1 ? 4 : 16);
-          sG[1 * st + 2 * sb2] += (T)(s * As * beta * qa);
-        }
-      }
-    }
-    __syncthreads();
-    expand_fibres<N, BLOCK, T, FIB>(acc, sU, sG, sY, 4, 4, 4, CS, pf);
-    __syncthreads();
-  }
+  expand_fibres<N, BLOCK, T, FIB>(acc, sFU, sFG, sY, 4, 4, 4, CS, pf);
+  __syncthreads();
 
   // far sides of the six faces
   for (int l = 0; l < kSlots; ++l) {
@@ -817,15 +817,15 @@ __global__ __launch_bounds__(BLOCK) void k_expand_plain(int CS, const double* co
 template <int N>
 struct ExpandShape;
 template <> struct ExpandShape<16> { static constexpr int B = 256; };
-template <> struct ExpandShape<24> { static constexpr int B = 288; };
-template <> struct ExpandShape<32> { static constexpr int B = 512; };
+template <> struct ExpandShape<24> { static constexpr int B = 576; };
+template <> struct ExpandShape<32> { static constexpr int B = 1024; };
 template <> struct ExpandShape<48> { static constexpr int B = 768; };
 
 template <int N, typename T>
 hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, hipStream_t s) {
   constexpr int B = ExpandShape<N>::B;
   const int CS = d.CS;
-  const size_t sh = sizeof(T) * (N + 3 * N + N + 3 * CS * N + CS * CS * CS + CS * CS * N);
+  const size_t sh = sizeof(T) * (N + 3 * N + N + 3 * CS * N + CS * CS * CS + CS * CS * N + 3 * CS * N + 64);
   auto k = k_expand<N, B, T>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
