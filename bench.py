@@ -83,9 +83,10 @@ def project_flops(N, ranks):
 
 
 def measured_traffic(workload_name, fam):
-    """HBM bytes per launch of a kernel family from the committed counter
-    summaries (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when
-    there is none for this workload or the kernel's source has changed since."""
+    """HBM bytes per cell of a kernel family from the committed counter
+    summaries (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated, divided by the
+    cells the profiled launches covered), or None when there is none for this
+    workload or the kernel's source has changed since."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
@@ -97,7 +98,7 @@ def measured_traffic(workload_name, fam):
         with open(os.path.join(ROOT, k["source"]), "rb") as fh:
             if hashlib.sha256(fh.read()).hexdigest() != k["sha256"]:
                 return None
-        return k["fetch_bytes"] + k["write_bytes"]
+        return k["fetch_bytes_per_cell"] + k["write_bytes_per_cell"]
     return None
 
 
@@ -120,8 +121,10 @@ def roofline(fam, cfg, mesh, res, steps):
     else:
         return None
     achieved = work / launches_per_step / per_launch_s / 1e12
+    per_cell = measured_traffic(cfg["name"], fam)
+    traffic = per_cell * nc / launches_per_step if per_cell is not None else None
     return {"bound": bound, "achieved": achieved, "peak": peak / 1e12, "unit": unit,
-            "frac": achieved / (peak / 1e12), "traffic": measured_traffic(cfg["name"], fam), "kernel": fam,
+            "frac": achieved / (peak / 1e12), "traffic": traffic, "kernel": fam,
             "avg_launch_ms": per_launch_s * 1e3, "launches_per_step": launches_per_step}
 
 
