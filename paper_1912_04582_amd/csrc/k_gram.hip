@@ -27,12 +27,14 @@ __device__ inline void ld4(const double* p, double (&o)[4]) {
 }
 
 template <int N, typename T>
-__global__ __launch_bounds__(64) void k_gram(const T* X, double* G) {
+__global__ __launch_bounds__(192) void k_gram(const T* X, double* G) {
   constexpr int NB = (N + 15) / 16;  // 16-row blocks
   constexpr int NP = NB * (NB + 1) / 2;
-  const int cell = blockIdx.x / 3;
-  const int mode = blockIdx.x % 3;
-  const int lane = threadIdx.x;
+  // one workgroup per cell, one wavefront per mode: the three waves read the
+  // same tensor at the same time, on the same CU
+  const int cell = blockIdx.x;
+  const int mode = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int ii = lane & 15;  // row within block (A) / column within block (B)
   const int kk = lane >> 4;  // k within the 4-wide step
   const T* x = X + (size_t)cell * N * N * N;
@@ -303,7 +305,7 @@ hipError_t launch_gram_lds_t(int count, const void* X, double* G, hipStream_t s)
 
 hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  dim3 grid(3 * count), blk(64);
+  dim3 grid(count), blk(192);
   if (mixed) {
     const float* x = (const float*)X;
     switch (N) {
