@@ -81,18 +81,25 @@ __global__ __launch_bounds__(kProjThreads) void k_project(const T* X, int c0, in
 // Variant for tensors whose first mode product fits the LDS: every thread
 // reads whole mode-1 fibres (N contiguous values, coalesced across the
 // workgroup) once, Y1 = W1^T A is kept in LDS, then Y2 = Y1 x2 W2^T and
-// C = Y2 x3 W3^T; two barriers in total.
+// C = Y2 x3 W3^T; two barriers in total.  The LDS is laid out for ranks up
+// to `cap` in modes 1 and 2.  A launch takes the cells whose ranks in modes 1
+// and 2 are at most `low_cap` when `take_low` is set, the others otherwise
+// (one launch of each covers every cell once, the first with room for
+// several workgroups per CU).
 template <int N, typename T>
 __global__ __launch_bounds__(kProjThreads) void k_project_fib(const T* X, int c0, int CS, const double* fac_n,
-                                                             const int* rank_n, double* core_n) {
+                                                             const int* rank_n, double* core_n, int cap,
+                                                             int low_cap, int take_low) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* sW = reinterpret_cast<double*>(smem_raw);  // 3 CS N
-  double* sY2 = sW + 3 * CS * N;                     // CS CS N
-  T* sY1 = reinterpret_cast<T*>(sY2 + CS * CS * N);  // CS N^2
+  double* sW = reinterpret_cast<double*>(smem_raw);    // 3 CS N
+  double* sY2 = sW + 3 * CS * N;                       // cap cap N
+  T* sY1 = reinterpret_cast<T*>(sY2 + cap * cap * N);  // cap N^2
   const int cl = blockIdx.x;
   const int cell = c0 + cl;
   const int tid = threadIdx.x;
   const int r1 = rank_n[3 * cell], r2 = rank_n[3 * cell + 1], r3 = rank_n[3 * cell + 2];
+  const bool is_low = r1 <= low_cap && r2 <= low_cap;
+  if (is_low != (take_low != 0)) return;
   for (int o = tid; o < 3 * CS * N; o += kProjThreads) sW[o] = fac_n[(size_t)cell * 3 * CS * N + o];
   __syncthreads();
   const T* x = X + (size_t)cl * N * N * N;
@@ -132,19 +139,28 @@ __global__ __launch_bounds__(kProjThreads) void k_project_fib(const T* X, int c0
 }
 
 template <int N, typename T>
-size_t project_fib_bytes(int CS) {
-  return sizeof(double) * (3 * (size_t)CS * N + (size_t)CS * CS * N) + sizeof(T) * (size_t)CS * N * N;
+size_t project_fib_bytes(int CS, int cap) {
+  return sizeof(double) * (3 * (size_t)CS * N + (size_t)cap * cap * N) + sizeof(T) * (size_t)cap * N * N;
 }
+
+// rank cap of the low-rank projection launch
+constexpr int kProjLowCap = 6;
 
 template <int N, typename T>
 hipError_t launch_project_t(int count, const void* X, int c0, int CS, const double* fac_n, const int* rank_n,
                             double* core_n, hipStream_t s) {
-  const size_t shf = project_fib_bytes<N, T>(CS);
+  const size_t shf = project_fib_bytes<N, T>(CS, CS);
   if (shf <= 96 * 1024) {
     auto k = k_project_fib<N, T>;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shf);
+    const int low = CS < kProjLowCap ? CS : kProjLowCap;
+    const size_t shl = project_fib_bytes<N, T>(CS, low);
+    const size_t shmax = shf > shl ? shf : shl;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmax);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(count), dim3(kProjThreads), shf, s, (const T*)X, c0, CS, fac_n, rank_n, core_n);
+    hipLaunchKernelGGL(k, dim3(count), dim3(kProjThreads), shl, s, (const T*)X, c0, CS, fac_n, rank_n, core_n, low,
+                       low, 1);
+    hipLaunchKernelGGL(k, dim3(count), dim3(kProjThreads), shf, s, (const T*)X, c0, CS, fac_n, rank_n, core_n, CS,
+                       low, 0);
     return hipGetLastError();
   }
   const size_t sh = sizeof(double) * (N * N + 3 * CS * N + CS * N + CS * CS);
