@@ -186,6 +186,25 @@ def test_plain_step_matches_full_update(ctx, precision, tol):
     st.close(); mesh.close()
 
 
+def test_mixed_long_run_tracks_fp64(ctx):
+    """Many warm-started steps (leading-block and full eigensolves, rank
+    growth near walls): the mixed path stays with the FP64 path.  Rank
+    decisions may differ at the truncation threshold, so the bar is the
+    tolerance-level drift, far above FP32 noise and far below an error."""
+    m, cfg = small_channel(N=24, cap=8, tol=1e-5, precision="mixed", nx=8)
+    m0 = synth.initial_macros(cfg, m)
+    mesh = tk.Mesh(ctx, m)
+    a = tk.State(ctx, mesh, cfg, m0)
+    b = tk.State(ctx, mesh, dict(cfg, precision="fp64"), m0)
+    for _ in range(4):
+        a.step(20)
+        b.step(20)
+    err, _ = macro_rel_err(a.moments(), b.moments())
+    print(f"mixed vs FP64, 80 steps: max rel macro err {err:.3e}")
+    assert err < 1e-3, err
+    a.close(); b.close(); mesh.close()
+
+
 def test_batch_equals_alone_and_oracle(ctx):
     """Instances advanced together give the same result as each alone."""
     specs = []
