@@ -27,6 +27,16 @@ namespace {
 
 constexpr int KC = 4;  // rank-1 chunk of the staged mode products
 
+// Workgroups per cell of the axis-aligned expansion.
+template <int N>
+struct ExpandSplit {
+  static constexpr int S = 1;
+};
+template <>
+struct ExpandSplit<32> {
+  static constexpr int S = 2;
+};
+
 // One source into the fibre accumulators: Y = G x3 U3 (all r1 x r2 x N in
 // LDS), then each thread forms z_j = sum_k2 U2[i2,k2] Y[j,k2,i3] for its own
 // fibres and adds U1[:,j] z_j.  One barrier between Y and its use; the
@@ -91,8 +101,11 @@ __device__ inline void stage_state(const double* core, const double* fac, int CS
 
 template <int N, int BLOCK, typename T>
 __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
-  constexpr int FIB = N * N / BLOCK;
-  static_assert(FIB * BLOCK == N * N, "fibres must tile the block");
+  // SPLIT workgroups share a cell, each expanding every source but only its
+  // share of the fibres (more, smaller workgroups per CU)
+  constexpr int SPLIT = ExpandSplit<N>::S;
+  constexpr int FIB = N * N / (BLOCK * SPLIT);
+  static_assert(FIB * BLOCK * SPLIT == N * N, "fibres must tile the workgroups");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const int CS = d.CS;
@@ -104,13 +117,14 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
   T* sY = sG + CS * CS * CS;      // CS CS N
   T* sFU = sY + CS * CS * N;      // 3 CS N   f_S factors
   T* sFG = sFU + 3 * CS * N;      // 64       f_S core
-  const int c = c0 + blockIdx.x;
+  const int cb = blockIdx.x / SPLIT, part = blockIdx.x % SPLIT;
+  const int c = c0 + cb;
   const int tid = threadIdx.x;
   const InstParams P = d.ip[d.inst[c]];
   const double nu = d.nu[c];
   int pf[FIB];
 #pragma unroll
-  for (int f = 0; f < FIB; ++f) pf[f] = tid + BLOCK * f;
+  for (int f = 0; f < FIB; ++f) pf[f] = tid + BLOCK * (part * FIB + f);
 
   for (int i = tid; i < N; i += BLOCK) {
     const double x = P.xi_min + i * P.dxi;
@@ -217,7 +231,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
     __syncthreads();
   }
 
-  T* out = X + (size_t)blockIdx.x * N * N * N;
+  T* out = X + (size_t)cb * N * N * N;
 #pragma unroll
   for (int f = 0; f < FIB; ++f)
 #pragma unroll
@@ -818,7 +832,7 @@ template <int N>
 struct ExpandShape;
 template <> struct ExpandShape<16> { static constexpr int B = 256; };
 template <> struct ExpandShape<24> { static constexpr int B = 576; };
-template <> struct ExpandShape<32> { static constexpr int B = 1024; };
+template <> struct ExpandShape<32> { static constexpr int B = 512; };
 template <> struct ExpandShape<48> { static constexpr int B = 768; };
 
 template <int N, typename T>
@@ -829,7 +843,7 @@ hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, hipStr
   auto k = k_expand<N, B, T>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(count), dim3(B), sh, s, d, c0, (T*)X);
+  hipLaunchKernelGGL(k, dim3(count * ExpandSplit<N>::S), dim3(B), sh, s, d, c0, (T*)X);
   return hipGetLastError();
 }
 
