@@ -181,6 +181,20 @@ tk_status tk_state_tune(tk_state* st, int32_t* steps_run);
  * The results are those of the eager launches.                           */
 tk_status tk_state_use_graph(tk_state* st, int32_t on);
 
+/* Restart checkpoints (Sec. "The program": a run is continued from a saved
+ * solution).  tk_state_checkpoint writes the whole state to host memory:
+ * the instances' step parameters (dt included), every cell's Tucker core,
+ * factors and ranks (or the full tensors of a plain state), the
+ * eigensolver's warm-start bases and whether they are in use.  With
+ * buf == NULL it only sets *needed; TK_EINVAL if bytes < *needed.  The
+ * buffer is the caller's.  tk_state_restore loads such a buffer into a
+ * state built from the same meshes, N, precision, rank cap and kind
+ * (checked against the buffer's header, TK_EINVAL otherwise); the steps
+ * that follow are then bit for bit those the saved state would have taken.
+ * Both wait for the context stream.                                       */
+tk_status tk_state_checkpoint(tk_state* st, void* buf, size_t bytes, size_t* needed);
+tk_status tk_state_restore(tk_state* st, const void* buf, size_t bytes);
+
 /* Macroparameters of every cell, out[n_cells][8] = (n, u1, u2, u3, T, q1,
  * q2, q3), computed on the device in FP64 from the Tucker state (Alg. 2
  * steps 1-9 by Op5 convolutions).  Blocking.                              */

@@ -968,6 +968,137 @@ tk_status tk_state_dt(const tk_state* st, int32_t inst, double* dt) {
   return TK_OK;
 }
 
+// ---- checkpoints -------------------------------------------------------------
+namespace {
+
+struct CkptHeader {
+  char magic[8];  // "TKCKPT1"
+  int32_t N, CS, nc, ninst, mixed, plain, warm, pad;
+};
+
+struct CkptLayout {
+  size_t ip, core, fac, rank, wkeep, f, total;
+};
+
+CkptLayout ckpt_layout(const tk_state* st) {
+  CkptLayout L{};
+  size_t o = sizeof(CkptHeader);
+  L.ip = o;
+  o += sizeof(tk::InstParams) * st->ninst;
+  const size_t nc = st->nc, N = st->N, CS = st->CS;
+  if (st->plain) {
+    L.f = o;
+    o += nc * N * N * N * (st->mixed ? 4 : 8);
+  } else {
+    L.core = o;
+    o += nc * CS * CS * CS * sizeof(double);
+    L.fac = o;
+    o += nc * 3 * CS * N * sizeof(double);
+    L.rank = o;
+    o += nc * 3 * sizeof(int);
+    L.wkeep = o;
+    o += nc * 3 * N * N * sizeof(double);
+  }
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+tk_status tk_state_checkpoint(tk_state* st, void* buf, size_t bytes, size_t* needed) {
+  if (!st) return TK_EINVAL;
+  tk_ctx* ctx = st->ctx;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  const CkptLayout L = ckpt_layout(st);
+  if (needed) *needed = L.total;
+  if (!buf) return TK_OK;
+  if (bytes < L.total) return ctx_fail(ctx, TK_EINVAL, "checkpoint buffer too small");
+  unsigned char* b = static_cast<unsigned char*>(buf);
+  CkptHeader h{};
+  std::memcpy(h.magic, "TKCKPT1", 8);
+  h.N = st->N;
+  h.CS = st->CS;
+  h.nc = st->nc;
+  h.ninst = st->ninst;
+  h.mixed = st->mixed ? 1 : 0;
+  h.plain = st->plain ? 1 : 0;
+  h.warm = st->warm ? 1 : 0;
+  std::memcpy(b, &h, sizeof(h));
+  std::memcpy(b + L.ip, st->ip_host.data(), sizeof(tk::InstParams) * st->ninst);
+  hipStream_t q = ctx->stream;
+  const size_t nc = st->nc, N = st->N, CS = st->CS;
+  hipError_t e = hipStreamSynchronize(q);
+  if (st->plain) {
+    if (e == hipSuccess) e = hipMemcpy(b + L.f, st->pf[st->cur], L.total - L.f, hipMemcpyDeviceToHost);
+  } else {
+    if (e == hipSuccess)
+      e = hipMemcpy(b + L.core, st->core[st->cur], nc * CS * CS * CS * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      e = hipMemcpy(b + L.fac, st->fac[st->cur], nc * 3 * CS * N * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(b + L.rank, st->rank[st->cur], nc * 3 * sizeof(int), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      e = hipMemcpy(b + L.wkeep, st->Wkeep, nc * 3 * N * N * sizeof(double), hipMemcpyDeviceToHost);
+  }
+  return ctx_hip(ctx, e, "checkpoint copy");
+}
+
+tk_status tk_state_restore(tk_state* st, const void* buf, size_t bytes) {
+  if (!st || !buf) return TK_EINVAL;
+  tk_ctx* ctx = st->ctx;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  const CkptLayout L = ckpt_layout(st);
+  const unsigned char* b = static_cast<const unsigned char*>(buf);
+  if (bytes < sizeof(CkptHeader)) return ctx_fail(ctx, TK_EINVAL, "restore: buffer too small");
+  CkptHeader h;
+  std::memcpy(&h, b, sizeof(h));
+  if (std::memcmp(h.magic, "TKCKPT1", 8) != 0) return ctx_fail(ctx, TK_EINVAL, "restore: not a checkpoint");
+  if (h.N != st->N || h.CS != st->CS || h.nc != st->nc || h.ninst != st->ninst || h.mixed != (st->mixed ? 1 : 0) ||
+      h.plain != (st->plain ? 1 : 0))
+    return ctx_fail(ctx, TK_EINVAL, "restore: checkpoint of a different state shape");
+  if (bytes < L.total) return ctx_fail(ctx, TK_EINVAL, "restore: buffer too small");
+  std::vector<tk::InstParams> ip(st->ninst);
+  std::memcpy(ip.data(), b + L.ip, sizeof(tk::InstParams) * st->ninst);
+  for (int k = 0; k < st->ninst; ++k)
+    if (ip[k].cap != st->ip_host[k].cap || ip[k].dxi != st->ip_host[k].dxi || ip[k].xi_min != st->ip_host[k].xi_min)
+      return ctx_fail(ctx, TK_EINVAL, "restore: checkpoint of different instance parameters");
+  hipStream_t q = ctx->stream;
+  const size_t nc = st->nc, N = st->N, CS = st->CS;
+  hipError_t e = hipStreamSynchronize(q);
+  if (e == hipSuccess) e = hipMemcpy(st->d_ip, ip.data(), sizeof(tk::InstParams) * st->ninst, hipMemcpyHostToDevice);
+  if (st->plain) {
+    if (e == hipSuccess) e = hipMemcpy(st->pf[st->cur], b + L.f, L.total - L.f, hipMemcpyHostToDevice);
+  } else {
+    if (e == hipSuccess)
+      e = hipMemcpy(st->core[st->cur], b + L.core, nc * CS * CS * CS * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(st->fac[st->cur], b + L.fac, nc * 3 * CS * N * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(st->rank[st->cur], b + L.rank, nc * 3 * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(st->Wkeep, b + L.wkeep, nc * 3 * N * N * sizeof(double), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return ctx_hip(ctx, e, "restore copy");
+  // the face coefficients dt A / V carry the checkpoint's dt
+  bool same_dt = true;
+  for (int k = 0; k < st->ninst; ++k) same_dt = same_dt && ip[k].dt == st->ip_host[k].dt;
+  if (!same_dt) {
+    std::vector<double> coef((size_t)st->nc * kSlots);
+    for (int k = 0; k < st->ninst; ++k) {
+      const tk_mesh* m = st->meshes[k];
+      const double dt = ip[k].dt;
+      for (int c = 0; c < m->n_cells; ++c)
+        for (int sl = 0; sl < kSlots; ++sl) {
+          const size_t src = (size_t)c * kSlots + sl, dst = ((size_t)st->inst_off[k] + c) * kSlots + sl;
+          coef[dst] = dt * m->slot_area[src] / m->volume[c];
+        }
+    }
+    e = hipMemcpy(st->d_slot_coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "restore face coefficients");
+  }
+  st->ip_host = ip;
+  st->warm = h.warm != 0;
+  return TK_OK;
+}
+
 tk_status tk_state_set_chunk(tk_state* st, int32_t cells) {
   if (!st) return TK_EINVAL;
   std::lock_guard<std::recursive_mutex> g(st->ctx->mu);

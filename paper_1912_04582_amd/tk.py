@@ -26,7 +26,7 @@ EXPORTED = [
     "tk_ctx_create", "tk_ctx_destroy", "tk_last_error", "tk_sync", "tk_prof_enable", "tk_prof_get",
     "tk_prof_reset", "tk_prof_eig", "tk_mesh_load", "tk_mesh_destroy", "tk_state_init", "tk_state_init_batch",
     "tk_state_destroy", "tk_state_info", "tk_state_dt", "tk_state_set_chunk", "tk_state_chunk",
-    "tk_state_tune", "tk_state_use_graph", "tk_moments", "tk_step", "tk_step_async",
+    "tk_state_tune", "tk_state_use_graph", "tk_state_checkpoint", "tk_state_restore", "tk_moments", "tk_step", "tk_step_async",
     "tk_state_ranks", "tk_state_export", "tk_round_tucker", "tk_plain_init", "tk_serve_create",
     "tk_serve_submit", "tk_serve_poll", "tk_serve_destroy",
 ]
@@ -105,6 +105,8 @@ def lib():
             "tk_state_chunk": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
             "tk_state_tune": [P, C.POINTER(C.c_int32)],
             "tk_state_use_graph": [P, C.c_int32],
+            "tk_state_checkpoint": [P, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)],
+            "tk_state_restore": [P, C.c_void_p, C.c_size_t],
             "tk_moments": [P, C.POINTER(C.c_double)],
             "tk_step": [P, C.c_int32, C.POINTER(C.c_double)],
             "tk_step_async": [P, C.c_int32],
@@ -307,6 +309,19 @@ class State:
         n = C.c_int32()
         _check(lib().tk_state_tune(self.h, C.byref(n)), self.ctx.h)
         return n.value
+
+    def checkpoint(self):
+        """The whole state as a host byte array (tk_state_checkpoint)."""
+        n = C.c_size_t()
+        _check(lib().tk_state_checkpoint(self.h, None, 0, C.byref(n)), self.ctx.h)
+        buf = np.zeros(n.value, dtype=np.uint8)
+        _check(lib().tk_state_checkpoint(self.h, buf.ctypes.data_as(C.c_void_p), buf.nbytes, C.byref(n)),
+               self.ctx.h)
+        return buf
+
+    def restore(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().tk_state_restore(self.h, buf.ctypes.data_as(C.c_void_p), buf.nbytes), self.ctx.h)
 
     def use_graph(self, on=True):
         _check(lib().tk_state_use_graph(self.h, 1 if on else 0), self.ctx.h)

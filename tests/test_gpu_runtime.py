@@ -139,3 +139,42 @@ def test_channel_full_size_sampled_cells():
 
 def test_jittered_box_full_size_sampled_cells():
     sampled_parity("cfg2", 2, 3, 1e-5)
+
+
+def small_channel_case(precision="mixed", N=16):
+    m = synth.channel_with_obstacle(nx=6, ny=4, nz=4, h=0.25, obstacle=((2, 3), (1, 2), (1, 3)),
+                                    inflow=(1.0, (0.8, 0.0, 0.0), 1.0), Tw=1.3)
+    cfg = dict(N=N, xi_max=4.5, cap=6, tol=1e-6, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=0.1, Rg=0.5, m=1.0,
+               seed=11, init="random", precision=precision)
+    return m, cfg, synth.initial_macros(cfg, m)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_checkpoint_restore_continues_bit_for_bit(ctx, plain):
+    m, cfg, m0 = small_channel_case()
+    mesh = tk.Mesh(ctx, m)
+    a = tk.State(ctx, mesh, cfg, m0, plain=plain)
+    a.step(5)
+    ck = a.checkpoint()
+    a.step(5)
+    # a state built from other initial fields (so another dt) takes the
+    # checkpoint's state and step parameters
+    other = m0.copy()
+    other[:, 4] *= 1.7
+    b = tk.State(ctx, mesh, cfg, other, plain=plain)
+    b.restore(ck)
+    b.step(5)
+    assert np.array_equal(a.moments(), b.moments())
+    if not plain:
+        assert np.array_equal(a.ranks()[0], b.ranks()[0])
+    # a checkpoint only fits a state of the same shape
+    m2, cfg2, m02 = small_channel_case(N=24)
+    c = tk.State(ctx, mesh, cfg2, m02, plain=plain)
+    with pytest.raises(tk.TkError) as ei:
+        c.restore(ck)
+    assert ei.value.status == tk.TK_EINVAL
+    with pytest.raises(tk.TkError):
+        c.restore(ck[:100])
+    for s in (a, b, c):
+        s.close()
+    mesh.close()
