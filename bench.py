@@ -334,6 +334,44 @@ def run_serve(count, max_steps, seed=4):
     return dict(saturated=sat, paced=paced, paced_half=half, rate=rate, cells=[q[0]["n_cells"] for q in reqs])
 
 
+def run_table1(steps, eps_list=(1e-3, 1e-4, 1e-5)):
+    """The paper's Table 1 on the synthetic channel: mean compression ratio
+    C = mean over cells of (r1 r2 r3 + N (r1 + r2 + r3)) / N^3 and the
+    relative 2-norm difference of the temperature field from the standard
+    (full-tensor) DVM after the same number of steps, for several rounding
+    tolerances.  Axis-aligned faces: both use the exact |xi_n|."""
+    cfg, mesh, m0 = workload("cfg1")
+    ctx = tk.Context(0)
+    rows = []
+    try:
+        tm = tk.Mesh(ctx, mesh)
+        p = tk.State(ctx, tm, cfg, m0, plain=True)
+        t0 = time.perf_counter()
+        p.step(steps)
+        tp = time.perf_counter() - t0
+        Tp = p.moments()[:, 4]
+        p.close()
+        log(f"table1: standard DVM {steps} steps, {1e3 * tp / steps:.2f} ms/step")
+        for eps in eps_list:
+            st = tk.State(ctx, tm, dict(cfg, tol=eps), m0)
+            st.tune()
+            st.close()
+            st = tk.State(ctx, tm, dict(cfg, tol=eps), m0)
+            t0 = time.perf_counter()
+            st.step(steps)
+            tt = time.perf_counter() - t0
+            T = st.moments()[:, 4]
+            _, C = st.ranks()
+            st.close()
+            dT = float(np.linalg.norm(T - Tp) / np.linalg.norm(Tp))
+            rows.append({"eps": eps, "mean_C": C, "dT_rel_2norm": dT, "ms_per_step": 1e3 * tt / steps})
+            log(f"table1: eps {eps:g}: C {C:.4g}, dT {dT:.3e}, {1e3 * tt / steps:.2f} ms/step")
+        tm.close()
+    finally:
+        ctx.close()
+    return {"standard_ms_per_step": 1e3 * tp / steps, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,6 +431,15 @@ def main():
         out["arrival_rate_half_per_s"] = 0.5 * r["rate"]
         out["value"] = out["paced"]["value"]
         print(json.dumps(out), flush=True)
+        return
+    if a.workload == "table1":
+        steps = a.steps or 200
+        r = run_table1(steps)
+        print(json.dumps({
+            "metric": "mean compression ratio and temperature difference vs the standard DVM (Table 1 style)",
+            "unit": "ratio", "n_gpus": 1, "steps": steps, "data": "synthetic",
+            "config": {"workload": "channel-64x32x32-obstacle-N32", "precision": "mixed", "cap": 12},
+            "standard_dvm_ms_per_step": r["standard_ms_per_step"], "rows": r["rows"]}), flush=True)
         return
     if a.workload == "batch":
         steps = a.steps or 50
