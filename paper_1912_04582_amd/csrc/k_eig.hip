@@ -287,7 +287,8 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
   }
   const double thr = tol * tol * tot / 3.0;
   const double abs_thr = abs_fac * fabs(tot);
-  if (k < N) {
+  // up to two leading blocks: r_prev + lead vectors, then 12 more
+  for (int attempt = 0; attempt < 2 && k < N; ++attempt) {
     // ---- leading block of the previous basis: B = W_k^T G W_k -------------
     for (int o = lane; o < N * k; o += NT) {
       const int i = o / k, j = o % k;
@@ -367,9 +368,11 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
       }
       return;
     }
-    // fall back to the full matrix
+    // fall back to a wider block, then to the full matrix
     for (int o = lane; o < N * N; o += NT) A[(o / N) * LD + o % N] = g[o];
     __syncthreads();
+    k += 12;
+    if (k > N) k = N;
   }
   if (wk) {
     // ---- full warm start: A <- V^T G V through Tm = G V --------------------
