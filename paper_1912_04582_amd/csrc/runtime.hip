@@ -658,7 +658,7 @@ static tk_status state_step_once(tk_state* st) {
     prof_begin(ctx, KID_EIG, &ev);
     if (st->mixed) {
       e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
-                     nullptr, st->Wkeep, 1e-12, 1e-16, q, 0.0, st->warm ? d.rank : nullptr, st->warm ? 8 : 0);
+                     nullptr, st->Wkeep, 1e-12, 1e-16, q, 0.0, st->warm ? d.rank : nullptr, st->warm ? 6 : 0);
     } else {
       // FP64 path: first basis, Gram of the rotated unfoldings, final basis
       e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
