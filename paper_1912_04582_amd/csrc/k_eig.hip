@@ -20,8 +20,8 @@
 // the rest of the spectrum carries at most 1e-3 of the truncation budget
 // eps^2 trace / 3 (its share then enters the discarded sum); the k x k
 // block W_k^T G W_k is diagonalised and the remaining basis vectors are kept.
-// A rank that comes within 2 of k, or a larger remainder, falls back to the
-// full matrix.  Rounds in
+// A rank that comes within 2 of k, or a larger remainder, retries with a
+// block 12 vectors wider, then falls back to the full matrix.  Rounds in
 // which no pair needs a rotation skip the update passes; convergence is
 // checked by a parallel scan of the off-diagonal elements before each sweep.
 //
