@@ -37,25 +37,26 @@ struct ExpandSplit<32> {
   static constexpr int S = 2;
 };
 
-// One source into the fibre accumulators: Y = G x3 U3 (all r1 x r2 x N in
-// LDS), then each thread forms z_j = sum_k2 U2[i2,k2] Y[j,k2,i3] for its own
-// fibres and adds U1[:,j] z_j.  One barrier between Y and its use; the
-// caller separates sources with a barrier before restaging.
-template <int N, int BLOCK, typename T, int FIB>
-__device__ inline void expand_fibres(T (&acc)[FIB][N], const T* sU, const T* sG, T* sY, int r1, int r2, int r3,
-                                     int CS, const int (&pf)[FIB]) {
-  const T* U1 = sU;
-  const T* U2 = sU + CS * N;
+// Y = G x3 U3 of one staged source, all r1 x r2 x N entries, into LDS.
+template <int N, int BLOCK, typename T>
+__device__ inline void y_stage(const T* sU, const T* sG, T* sY, int r1, int r2, int r3, int CS) {
   const T* U3 = sU + 2 * CS * N;
-  const int tid = threadIdx.x;
-  for (int o = tid; o < r1 * r2 * N; o += BLOCK) {
+  for (int o = threadIdx.x; o < r1 * r2 * N; o += BLOCK) {
     const int i3 = o % N, t = o / N, k2 = t % r2, j = t / r2;
     T sacc = 0;
     const T* g = sG + j + r1 * k2;
     for (int k3 = 0; k3 < r3; ++k3) sacc += g[r1 * r2 * k3] * U3[k3 * N + i3];
     sY[o] = sacc;
   }
-  __syncthreads();
+}
+
+// Mode-2 and mode-1 products of one source whose Y is in LDS, for the
+// thread's own fibres: z_j = sum_k2 U2[i2,k2] Y[j,k2,i3], acc += U1[:,j] z_j.
+template <int N, typename T, int FIB>
+__device__ inline void fibre_products(T (&acc)[FIB][N], const T* sU, const T* sY, int r1, int r2, int CS,
+                                      const int (&pf)[FIB]) {
+  const T* U1 = sU;
+  const T* U2 = sU + CS * N;
   for (int j = 0; j < r1; ++j) {
     T z[FIB];
 #pragma unroll
@@ -74,6 +75,18 @@ __device__ inline void expand_fibres(T (&acc)[FIB][N], const T* sU, const T* sG,
       for (int f = 0; f < FIB; ++f) acc[f][i1] += uv * z[f];
     }
   }
+}
+
+// One source into the fibre accumulators: Y = G x3 U3 (all r1 x r2 x N in
+// LDS), then each thread forms z_j = sum_k2 U2[i2,k2] Y[j,k2,i3] for its own
+// fibres and adds U1[:,j] z_j.  One barrier between Y and its use; the
+// caller separates sources with a barrier before restaging.
+template <int N, int BLOCK, typename T, int FIB>
+__device__ inline void expand_fibres(T (&acc)[FIB][N], const T* sU, const T* sG, T* sY, int r1, int r2, int r3,
+                                     int CS, const int (&pf)[FIB]) {
+  y_stage<N, BLOCK, T>(sU, sG, sY, r1, r2, r3, CS);
+  __syncthreads();
+  fibre_products<N, T, FIB>(acc, sU, sY, r1, r2, CS, pf);
 }
 
 // Stage a state-layout Tucker tensor into LDS.  rev_axis: mode whose rows
@@ -236,6 +249,348 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
   for (int f = 0; f < FIB; ++f)
 #pragma unroll
     for (int i = 0; i < N; ++i) out[(size_t)pf[f] * N + i] = acc[f][i];
+}
+
+// ---------------------------------------------------------------------------
+// The same assembly with the sources software-pipelined.  The cell's face
+// records and the far cells' ranks are read once, by one thread per face,
+// into LDS; each source is staged into one of two LDS buffers, and the
+// global loads of the next source are issued before the current source's
+// fibre products, so their latency is hidden behind arithmetic.  Used when
+// two buffers leave room for two workgroups per CU.  At N = 32 in FP32 the
+// last two mode products run on the matrix cores (tile_products): the
+// fibre form reads all of U1[:, j] from LDS for every 32 FMAs of a wave,
+// which on the CU's shared LDS takes about twice the time of the FMAs.
+
+enum : int { SRC_STATE = 0, SRC_FS = 1, SRC_BC = 2 };
+
+// one source: its kind, the cell or boundary index, ranks, the reversed
+// axis (symmetry ghost), the scaled axis with b(i) = coef max(-sig xi_i, 0)
+// and the core scale
+struct ExpSrc {
+  int type, idx, q1, q2, q3, rev, sax;
+  double coef, sig, gsc;
+};
+
+// this thread's share of a source's global data: one value per mode factor
+// (threads below q_a N), the first core value, or one boundary factor value
+struct ExpPre {
+  double f0, f1, f2, g;
+};
+
+template <int N>
+__device__ inline int fac_index(int tid, int rev_axis, int a) {
+  const int i = tid % N;
+  return (tid / N) * N + ((a == rev_axis) ? (N - 1 - i) : i);
+}
+
+template <int N>
+__device__ inline void src_prefetch(const DevState& d, const ExpSrc& e, ExpPre& p) {
+  const int tid = threadIdx.x;
+  const int CS = d.CS;
+  p.f0 = p.f1 = p.f2 = p.g = 0.0;
+  if (e.type == SRC_STATE) {
+    const double* fa = d.fac + (size_t)e.idx * 3 * CS * N;
+    if (tid < e.q1 * N) p.f0 = fa[fac_index<N>(tid, e.rev, 0)];
+    if (tid < e.q2 * N) p.f1 = fa[CS * N + fac_index<N>(tid, e.rev, 1)];
+    if (tid < e.q3 * N) p.f2 = fa[2 * CS * N + fac_index<N>(tid, e.rev, 2)];
+    if (tid < e.q1 * e.q2 * e.q3) {
+      const int k1 = tid % e.q1, t = tid / e.q1, k2 = t % e.q2, k3 = t / e.q2;
+      p.g = d.core[(size_t)e.idx * CS * CS * CS + k1 + CS * (k2 + CS * k3)];
+    }
+  } else if (e.type == SRC_BC) {
+    if (tid < 3 * N) p.f0 = d.bc_fac[(size_t)e.idx * 3 * N + tid];
+  }
+}
+
+template <int N, int BLOCK, typename T>
+__device__ inline void src_store(const DevState& d, const InstParams& P, const ExpSrc& e, const ExpPre& p, T* sU,
+                                 T* sG) {
+  const int tid = threadIdx.x;
+  const int CS = d.CS;
+  auto scale = [&](int i) -> T { return (T)(e.coef * fmax(-e.sig * (P.xi_min + i * P.dxi), 0.0)); };
+  if (e.type == SRC_STATE) {
+    const double fv[3] = {p.f0, p.f1, p.f2};
+    const int qq[3] = {e.q1, e.q2, e.q3};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (tid < qq[a] * N) {
+        T v = (T)fv[a];
+        if (a == e.sax) v *= scale(tid % N);
+        sU[a * CS * N + tid] = v;
+      }
+    }
+    const int nq = e.q1 * e.q2 * e.q3;
+    if (tid < nq) sG[tid] = (T)(p.g * 1.0);
+    for (int o = tid + BLOCK; o < nq; o += BLOCK) {
+      const int k1 = o % e.q1, t = o / e.q1, k2 = t % e.q2, k3 = t / e.q2;
+      sG[o] = (T)(d.core[(size_t)e.idx * CS * CS * CS + k1 + CS * (k2 + CS * k3)] * 1.0);
+    }
+  } else if (e.type == SRC_BC) {
+    if (tid < 3 * N) {
+      const int a = tid / N, i = tid % N;
+      T v = (T)p.f0;
+      if (a == e.sax) v *= scale(i);
+      sU[a * CS * N + i] = v;
+    }
+    if (tid == 0) sG[0] = (T)e.gsc;
+  }
+}
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Last two mode products of one source on the matrix cores (N = 32, FP32):
+// for the wave's tiles X[i1, i2, i3] (i3 = i3a, i3a + 1; all i1, i2),
+//   X^T[i2, i1] += sum_j Z_j[i2, i3] U1[i1, j],  Z_j = U2 Y_j,
+// two values of j per v_mfma_f32_32x32x2f32.  Lane l supplies the A value
+// at row l % 32, k = l / 32 (z of j = j0 + l / 32 at i2 = l % 32, formed by
+// the lane itself) and the B value at k = l / 32, column l % 32 (U1[l % 32,
+// j]); it holds D rows 8 (v / 4) + 4 (l / 32) + v % 4 of column l % 32.
+__device__ inline void tile_products(v16f& t0, v16f& t1, const float* sU, const float* sY, int r1, int r2, int CS,
+                                     int li, int hi, int i3a) {
+  constexpr int N = 32;
+  const float* U1 = sU;
+  const float* U2 = sU + CS * N;
+  for (int j0 = 0; j0 < r1; j0 += 2) {
+    const int j = j0 + hi;
+    float z0 = 0.f, z1 = 0.f, u1 = 0.f;
+    if (j < r1) {
+      const float* y = sY + j * r2 * N + i3a;
+      for (int k2 = 0; k2 < r2; ++k2) {
+        const float u2 = U2[k2 * N + li];
+        const float2 yy = *reinterpret_cast<const float2*>(y + k2 * N);
+        z0 += u2 * yy.x;
+        z1 += u2 * yy.y;
+      }
+      u1 = U1[j * N + li];
+    }
+    t0 = __builtin_amdgcn_mfma_f32_32x32x2f32(z0, u1, t0, 0, 0, 0);
+    t1 = __builtin_amdgcn_mfma_f32_32x32x2f32(z1, u1, t1, 0, 0, 0);
+  }
+}
+
+template <int N, int BLOCK, typename T, bool MF>
+__global__ __launch_bounds__(BLOCK) void k_expand_pipe(DevState d, int c0, T* X) {
+  constexpr int SPLIT = ExpandSplit<N>::S;
+  constexpr int FIB = N * N / (BLOCK * SPLIT);
+  static_assert(FIB * BLOCK * SPLIT == N * N, "fibres must tile the workgroups");
+  static_assert(BLOCK >= N * kMaxCap && BLOCK >= 3 * N, "one factor value per thread and mode");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ ExpSrc s_slot[kSlots];     // per face, as stored
+  __shared__ ExpSrc s_src[2 + kSlots];  // own cell, f_S, then the used faces
+  __shared__ int s_ns;
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int CS = d.CS;
+  const int GS = (CS * CS * CS + 1) & ~1;                // core extent, even so Y stays 8-byte aligned
+  const int BUF = 3 * CS * N + GS + CS * CS * N;         // sU, sG, sY of one buffer
+  T* sd = smem;                   // 3 N   own-cell outflow tables d_a
+  T* sFU = sd + 3 * N;            // 3 CS N   f_S factors
+  T* sFG = sFU + 3 * CS * N;      // 64       f_S core
+  T* sB = sFG + 64;               // two buffers
+  const int cb = blockIdx.x / SPLIT, part = blockIdx.x % SPLIT;
+  const int c = c0 + cb;
+  const int tid = threadIdx.x;
+  const InstParams P = d.ip[d.inst[c]];
+  const double nu = d.nu[c];
+  int pf[FIB];
+#pragma unroll
+  for (int f = 0; f < FIB; ++f) pf[f] = tid + BLOCK * (part * FIB + f);
+
+  // face records: one thread per slot, each one round of loads (plus the
+  // far cell's ranks)
+  if (tid < kSlots) {
+    const size_t sl = (size_t)kSlots * c + tid;
+    const int kind = d.slot_kind[sl];
+    ExpSrc e;
+    e.type = -1;
+    e.idx = d.slot_nb[sl];
+    e.q1 = e.q2 = e.q3 = 1;
+    e.rev = -1;
+    e.sax = d.slot_axis[sl];
+    e.coef = d.slot_coef[sl];
+    e.sig = (double)d.slot_sig[sl];
+    e.gsc = 1.0;
+    if (kind == SK_INTERIOR || kind == SK_OUTFLOW || kind == SK_SYM) {
+      e.type = SRC_STATE;
+      if (kind != SK_INTERIOR) e.idx = c;
+      if (kind == SK_SYM) e.rev = e.sax;
+      e.q1 = d.rank[3 * e.idx];
+      e.q2 = d.rank[3 * e.idx + 1];
+      e.q3 = d.rank[3 * e.idx + 2];
+    } else if (kind != SK_NONE) {
+      e.type = SRC_BC;
+      if (kind == SK_WALL) e.gsc = d.nw[sl];
+    }
+    s_slot[tid] = e;
+  }
+  if (tid == 0) {
+    ExpSrc e;
+    e.type = SRC_STATE;
+    e.idx = c;
+    e.q1 = d.rank[3 * c];
+    e.q2 = d.rank[3 * c + 1];
+    e.q3 = d.rank[3 * c + 2];
+    e.rev = e.sax = -1;
+    e.coef = e.sig = 0.0;
+    e.gsc = 1.0;
+    s_src[0] = e;
+    e.type = SRC_FS;
+    e.q1 = e.q2 = e.q3 = 4;
+    s_src[1] = e;
+  }
+  // the own cell's data, in flight while f_S is set up
+  ExpPre pre;
+  {
+    ExpSrc own;
+    own.type = SRC_STATE;
+    own.idx = c;
+    own.q1 = d.rank[3 * c];
+    own.q2 = d.rank[3 * c + 1];
+    own.q3 = d.rank[3 * c + 2];
+    own.rev = own.sax = -1;
+    own.coef = own.sig = 0.0;
+    own.gsc = 1.0;
+    src_prefetch<N>(d, own, pre);
+  }
+  // f_S in Tucker form, scaled by dt nu
+  {
+    const double* M = d.macro + 8 * (size_t)c;
+    const double n = M[0], T0 = M[4];
+    const double RT = P.Rg * T0;
+    const double amp = cbrt(n) / sqrt(2.0 * M_PI * RT);
+    const double beta = 1.0 / (2.0 * RT);
+    const double As = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * n * RT * RT);
+    for (int o = tid; o < 3 * N; o += BLOCK) {
+      const int a = o / N, i = o % N;
+      const double v = P.xi_min + i * P.dxi - M[1 + a];
+      const double base = amp * exp(-v * v * beta);
+      sFU[a * CS * N + 0 * N + i] = (T)base;
+      sFU[a * CS * N + 1 * N + i] = (T)(base * v);
+      sFU[a * CS * N + 2 * N + i] = (T)(base * v * v);
+      sFU[a * CS * N + 3 * N + i] = (T)(base * v * v * v);
+    }
+    if (tid == 0) {
+      for (int o = 0; o < 64; ++o) sFG[o] = 0;
+      const double sc = P.dt * nu;
+      sFG[0] = (T)sc;
+      for (int a = 0; a < 3; ++a) {
+        const double qa = M[5 + a];
+        int st = (a == 0) ? 1 : (a == 1 ? 4 : 16);
+        sFG[1 * st] += (T)(sc * -2.5 * As * qa);
+        sFG[3 * st] += (T)(sc * As * beta * qa);
+        for (int b2 = 0; b2 < 3; ++b2) {
+          if (b2 == a) continue;
+          const int sb2 = (b2 == 0) ? 1 : (b2 == 1 ? 4 : 16);
+          sFG[1 * st + 2 * sb2] += (T)(sc * As * beta * qa);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // compact the source list (unused slots dropped), the own-cell outflow
+  // tables, and the own cell into buffer 0
+  if (tid == 0) {
+    int n = 2;
+    for (int l = 0; l < kSlots; ++l)
+      if (s_slot[l].type >= 0) s_src[n++] = s_slot[l];
+    s_ns = n;
+  }
+  for (int i = tid; i < N; i += BLOCK) {
+    const double x = P.xi_min + i * P.dxi;
+    for (int a = 0; a < 3; ++a) {
+      double sacc = 0.0;
+      for (int l = 0; l < kSlots; ++l) {
+        const ExpSrc& e = s_slot[l];
+        if (e.type < 0 || e.sax != a) continue;
+        sacc -= e.coef * fmax(e.sig * x, 0.0);
+      }
+      sd[a * N + i] = (T)sacc;
+    }
+  }
+  src_store<N, BLOCK, T>(d, P, s_src[0], pre, sB, sB + 3 * CS * N);
+  __syncthreads();
+  y_stage<N, BLOCK, T>(sB, sB + 3 * CS * N, sB + 3 * CS * N + GS, s_src[0].q1, s_src[0].q2, s_src[0].q3,
+                       CS);
+  __syncthreads();
+
+  // VALU path: whole mode-1 fibres per thread.  MFMA path (MF): each wave
+  // owns the 32 x 32 tiles (i2 x i1) of two consecutive i3.
+  T acc[FIB][N];
+  v16f t0, t1;
+  const int lane = tid & 63, li = lane & 31, hi = lane >> 5;
+  const int i3a = 2 * (part * (BLOCK / 64) + (tid >> 6));
+  if constexpr (MF) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) t0[v] = t1[v] = 0.f;
+  } else {
+#pragma unroll
+    for (int f = 0; f < FIB; ++f)
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[f][i] = 0;
+  }
+  const int ns = s_ns;
+  for (int sidx = 0; sidx < ns; ++sidx) {
+    T* cur = sB + (sidx & 1) * BUF;
+    T* nxt = sB + ((sidx + 1) & 1) * BUF;
+    const ExpSrc& e = s_src[sidx];
+    const bool more = sidx + 1 < ns;
+    if (more) src_prefetch<N>(d, s_src[sidx + 1], pre);
+    const T* su = e.type == SRC_FS ? sFU : cur;
+    const T* sy = cur + 3 * CS * N + GS;
+    if constexpr (MF) {
+      tile_products(t0, t1, (const float*)su, (const float*)sy, e.q1, e.q2, CS, li, hi, i3a);
+    } else {
+      fibre_products<N, T, FIB>(acc, su, sy, e.q1, e.q2, CS, pf);
+    }
+    if (sidx == 0) {
+      const T cterm = (T)(1.0 - P.dt * nu);
+      if constexpr (MF) {
+        // tile element v of this lane: i1 = li, i2 = 8 (v / 4) + 4 hi + v % 4
+        const T s0 = sd[li];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int i2 = 8 * (v / 4) + 4 * hi + v % 4;
+          const T da = cterm + sd[N + i2] + sd[2 * N + i3a];
+          const T db = cterm + sd[N + i2] + sd[2 * N + i3a + 1];
+          t0[v] *= (s0 + da);
+          t1[v] *= (s0 + db);
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < FIB; ++f) {
+          const T dd = cterm + sd[N + pf[f] % N] + sd[2 * N + pf[f] / N];
+#pragma unroll
+          for (int i = 0; i < N; ++i) acc[f][i] *= (sd[i] + dd);
+        }
+      }
+    }
+    if (more) {
+      const ExpSrc& en = s_src[sidx + 1];
+      src_store<N, BLOCK, T>(d, P, en, pre, nxt, nxt + 3 * CS * N);
+      __syncthreads();
+      if (en.type == SRC_FS)
+        y_stage<N, BLOCK, T>(sFU, sFG, nxt + 3 * CS * N + GS, 4, 4, 4, CS);
+      else
+        y_stage<N, BLOCK, T>(nxt, nxt + 3 * CS * N, nxt + 3 * CS * N + GS, en.q1, en.q2, en.q3, CS);
+      __syncthreads();
+    }
+  }
+
+  T* out = X + (size_t)cb * N * N * N;
+  if constexpr (MF) {
+    // rows of 32 consecutive i1 per half-wave: coalesced 128-byte stores
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i2 = 8 * (v / 4) + 4 * hi + v % 4;
+      out[((size_t)i3a * N + i2) * N + li] = t0[v];
+      out[((size_t)(i3a + 1) * N + i2) * N + li] = t1[v];
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < FIB; ++f)
+#pragma unroll
+      for (int i = 0; i < N; ++i) out[(size_t)pf[f] * N + i] = acc[f][i];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -839,6 +1194,17 @@ template <int N, typename T>
 hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, hipStream_t s) {
   constexpr int B = ExpandShape<N>::B;
   const int CS = d.CS;
+  const size_t buf = 3 * CS * N + ((CS * CS * CS + 1) & ~1) + CS * CS * N;
+  const size_t sp = sizeof(T) * (3 * N + 3 * CS * N + 64 + 2 * buf);
+  if (sp <= 80 * 1024) {
+    // two buffers still leave room for two workgroups per CU
+    constexpr bool MF = (N == 32 && B == 512 && ExpandSplit<N>::S == 2 && sizeof(T) == 4);
+    auto k = k_expand_pipe<N, B, T, MF>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sp);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(count * ExpandSplit<N>::S), dim3(B), sp, s, d, c0, (T*)X);
+    return hipGetLastError();
+  }
   const size_t sh = sizeof(T) * (N + 3 * N + N + 3 * CS * N + CS * CS * CS + CS * CS * N + 3 * CS * N + 64);
   auto k = k_expand<N, B, T>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
