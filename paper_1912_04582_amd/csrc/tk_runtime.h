@@ -57,6 +57,7 @@ struct tk_state {
   // pass-size tuning: 0 fixed, 1 tuning; the trial steps and their events
   int tune = 0;
   int tune_step = 0;
+  int tune_skip = 0;  // untimed steps left before the trials
   std::vector<int> tune_cand;
   std::vector<hipEvent_t> tune_ev;
   // graph replay of a step, one graph per buffer parity
