@@ -305,7 +305,7 @@ __device__ inline void src_prefetch(const DevState& d, const ExpSrc& e, ExpPre& 
 
 template <int N, int BLOCK, typename T>
 __device__ inline void src_store(const DevState& d, const InstParams& P, const ExpSrc& e, const ExpPre& p, T* sU,
-                                 T* sG) {
+                                 T* sG, int LS) {
   const int tid = threadIdx.x;
   const int CS = d.CS;
   auto scale = [&](int i) -> T { return (T)(e.coef * fmax(-e.sig * (P.xi_min + i * P.dxi), 0.0)); };
@@ -317,7 +317,7 @@ __device__ inline void src_store(const DevState& d, const InstParams& P, const E
       if (tid < qq[a] * N) {
         T v = (T)fv[a];
         if (a == e.sax) v *= scale(tid % N);
-        sU[a * CS * N + tid] = v;
+        sU[a * LS * N + tid] = v;
       }
     }
     const int nq = e.q1 * e.q2 * e.q3;
@@ -331,7 +331,7 @@ __device__ inline void src_store(const DevState& d, const InstParams& P, const E
       const int a = tid / N, i = tid % N;
       T v = (T)p.f0;
       if (a == e.sax) v *= scale(i);
-      sU[a * CS * N + i] = v;
+      sU[a * LS * N + i] = v;
     }
     if (tid == 0) sG[0] = (T)e.gsc;
   }
@@ -369,8 +369,13 @@ __device__ inline void tile_products(v16f& t0, v16f& t1, const float* sU, const 
   }
 }
 
-template <int N, int BLOCK, typename T, bool MF>
-__global__ __launch_bounds__(BLOCK) void k_expand_pipe(DevState d, int c0, T* X) {
+// RB > 0: LDS laid out for ranks up to RB (more workgroups per CU); a cell
+// with a larger rank among its sources is appended to `list` and left to a
+// second launch.  LIST: 0 every cell of the pass, 1 as 0 with that
+// hand-off, 2 only the cells in `list` (the count in *list_n).
+template <int N, int BLOCK, typename T, bool MF, int RB, int LIST>
+__global__ __launch_bounds__(BLOCK, RB > 0 ? 6 : 1) void k_expand_pipe(DevState d, int c0, T* X, int* list,
+                                                                       int* list_n) {
   constexpr int SPLIT = ExpandSplit<N>::S;
   constexpr int FIB = N * N / (BLOCK * SPLIT);
   static_assert(FIB * BLOCK * SPLIT == N * N, "fibres must tile the workgroups");
@@ -380,14 +385,19 @@ __global__ __launch_bounds__(BLOCK) void k_expand_pipe(DevState d, int c0, T* X)
   __shared__ ExpSrc s_src[2 + kSlots];  // own cell, f_S, then the used faces
   __shared__ int s_ns;
   T* smem = reinterpret_cast<T*>(smem_raw);
-  const int CS = d.CS;
-  const int GS = (CS * CS * CS + 1) & ~1;                // core extent, even so Y stays 8-byte aligned
-  const int BUF = 3 * CS * N + GS + CS * CS * N;         // sU, sG, sY of one buffer
+  const int LS = RB > 0 ? RB : d.CS;                     // rank extent of the LDS layout
+  const int GS = (LS * LS * LS + 1) & ~1;                // core extent, even so Y stays 8-byte aligned
+  const int BUF = 3 * LS * N + GS + LS * LS * N;         // sU, sG, sY of one buffer
   T* sd = smem;                   // 3 N   own-cell outflow tables d_a
-  T* sFU = sd + 3 * N;            // 3 CS N   f_S factors
-  T* sFG = sFU + 3 * CS * N;      // 64       f_S core
+  T* sFU = sd + 3 * N;            // 3 LS N   f_S factors
+  T* sFG = sFU + 3 * LS * N;      // 64       f_S core
   T* sB = sFG + 64;               // two buffers
-  const int cb = blockIdx.x / SPLIT, part = blockIdx.x % SPLIT;
+  const int part = blockIdx.x % SPLIT;
+  int cb = blockIdx.x / SPLIT;
+  if constexpr (LIST == 2) {
+    if (cb >= *list_n) return;
+    cb = list[cb];
+  }
   const int c = c0 + cb;
   const int tid = threadIdx.x;
   const InstParams P = d.ip[d.inst[c]];
@@ -464,10 +474,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand_pipe(DevState d, int c0, T* X)
       const int a = o / N, i = o % N;
       const double v = P.xi_min + i * P.dxi - M[1 + a];
       const double base = amp * exp(-v * v * beta);
-      sFU[a * CS * N + 0 * N + i] = (T)base;
-      sFU[a * CS * N + 1 * N + i] = (T)(base * v);
-      sFU[a * CS * N + 2 * N + i] = (T)(base * v * v);
-      sFU[a * CS * N + 3 * N + i] = (T)(base * v * v * v);
+      sFU[a * LS * N + 0 * N + i] = (T)base;
+      sFU[a * LS * N + 1 * N + i] = (T)(base * v);
+      sFU[a * LS * N + 2 * N + i] = (T)(base * v * v);
+      sFU[a * LS * N + 3 * N + i] = (T)(base * v * v * v);
     }
     if (tid == 0) {
       for (int o = 0; o < 64; ++o) sFG[o] = 0;
@@ -487,6 +497,16 @@ __global__ __launch_bounds__(BLOCK) void k_expand_pipe(DevState d, int c0, T* X)
     }
   }
   __syncthreads();
+  if constexpr (LIST == 1) {
+    // every source must fit the RB layout; otherwise hand the cell over
+    int qm = max(s_src[0].q1, max(s_src[0].q2, s_src[0].q3));
+    for (int l = 0; l < kSlots; ++l)
+      if (s_slot[l].type == SRC_STATE) qm = max(qm, max(s_slot[l].q1, max(s_slot[l].q2, s_slot[l].q3)));
+    if (qm > RB) {
+      if (tid == 0 && part == 0) list[atomicAdd(list_n, 1)] = cb;
+      return;
+    }
+  }
   // compact the source list (unused slots dropped), the own-cell outflow
   // tables, and the own cell into buffer 0
   if (tid == 0) {
@@ -507,10 +527,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand_pipe(DevState d, int c0, T* X)
       sd[a * N + i] = (T)sacc;
     }
   }
-  src_store<N, BLOCK, T>(d, P, s_src[0], pre, sB, sB + 3 * CS * N);
+  src_store<N, BLOCK, T>(d, P, s_src[0], pre, sB, sB + 3 * LS * N, LS);
   __syncthreads();
-  y_stage<N, BLOCK, T>(sB, sB + 3 * CS * N, sB + 3 * CS * N + GS, s_src[0].q1, s_src[0].q2, s_src[0].q3,
-                       CS);
+  y_stage<N, BLOCK, T>(sB, sB + 3 * LS * N, sB + 3 * LS * N + GS, s_src[0].q1, s_src[0].q2, s_src[0].q3,
+                       LS);
   __syncthreads();
 
   // VALU path: whole mode-1 fibres per thread.  MFMA path (MF): each wave
@@ -536,11 +556,11 @@ __global__ __launch_bounds__(BLOCK) void k_expand_pipe(DevState d, int c0, T* X)
     const bool more = sidx + 1 < ns;
     if (more) src_prefetch<N>(d, s_src[sidx + 1], pre);
     const T* su = e.type == SRC_FS ? sFU : cur;
-    const T* sy = cur + 3 * CS * N + GS;
+    const T* sy = cur + 3 * LS * N + GS;
     if constexpr (MF) {
-      tile_products(t0, t1, (const float*)su, (const float*)sy, e.q1, e.q2, CS, li, hi, i3a);
+      tile_products(t0, t1, (const float*)su, (const float*)sy, e.q1, e.q2, LS, li, hi, i3a);
     } else {
-      fibre_products<N, T, FIB>(acc, su, sy, e.q1, e.q2, CS, pf);
+      fibre_products<N, T, FIB>(acc, su, sy, e.q1, e.q2, LS, pf);
     }
     if (sidx == 0) {
       const T cterm = (T)(1.0 - P.dt * nu);
@@ -566,12 +586,12 @@ __global__ __launch_bounds__(BLOCK) void k_expand_pipe(DevState d, int c0, T* X)
     }
     if (more) {
       const ExpSrc& en = s_src[sidx + 1];
-      src_store<N, BLOCK, T>(d, P, en, pre, nxt, nxt + 3 * CS * N);
+      src_store<N, BLOCK, T>(d, P, en, pre, nxt, nxt + 3 * LS * N, LS);
       __syncthreads();
       if (en.type == SRC_FS)
-        y_stage<N, BLOCK, T>(sFU, sFG, nxt + 3 * CS * N + GS, 4, 4, 4, CS);
+        y_stage<N, BLOCK, T>(sFU, sFG, nxt + 3 * LS * N + GS, 4, 4, 4, LS);
       else
-        y_stage<N, BLOCK, T>(nxt, nxt + 3 * CS * N, nxt + 3 * CS * N + GS, en.q1, en.q2, en.q3, CS);
+        y_stage<N, BLOCK, T>(nxt, nxt + 3 * LS * N, nxt + 3 * LS * N + GS, en.q1, en.q2, en.q3, LS);
       __syncthreads();
     }
   }
@@ -1190,19 +1210,39 @@ template <> struct ExpandShape<24> { static constexpr int B = 576; };
 template <> struct ExpandShape<32> { static constexpr int B = 512; };
 template <> struct ExpandShape<48> { static constexpr int B = 768; };
 
+// rank bound of the small-LDS expansion launch
+constexpr int kExpRB = 8;
+
 template <int N, typename T>
-hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, hipStream_t s) {
+hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, int* list, int* list_n, hipStream_t s) {
   constexpr int B = ExpandShape<N>::B;
   const int CS = d.CS;
   const size_t buf = 3 * CS * N + ((CS * CS * CS + 1) & ~1) + CS * CS * N;
   const size_t sp = sizeof(T) * (3 * N + 3 * CS * N + 64 + 2 * buf);
+  constexpr bool MF = (N == 32 && B == 512 && ExpandSplit<N>::S == 2 && sizeof(T) == 4);
+  const dim3 grid(count * ExpandSplit<N>::S);
+  if (MF && CS > kExpRB && list && list_n) {
+    // cells whose sources all have ranks <= kExpRB: a small LDS layout, three
+    // workgroups per CU; the rest through the full layout, from the list
+    constexpr int RB = kExpRB;
+    const size_t bufs = 3 * RB * N + ((RB * RB * RB + 1) & ~1) + RB * RB * N;
+    const size_t ss = sizeof(T) * (3 * N + 3 * RB * N + 64 + 2 * bufs);
+    auto kf = k_expand_pipe<N, B, T, MF, RB, 1>;
+    auto kl = k_expand_pipe<N, B, T, MF, 0, 2>;
+    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ss);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)kl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sp);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, list_n);
+    hipLaunchKernelGGL(kf, grid, dim3(B), ss, s, d, c0, (T*)X, list, list_n);
+    hipLaunchKernelGGL(kl, grid, dim3(B), sp, s, d, c0, (T*)X, list, list_n);
+    return hipGetLastError();
+  }
   if (sp <= 80 * 1024) {
     // two buffers still leave room for two workgroups per CU
-    constexpr bool MF = (N == 32 && B == 512 && ExpandSplit<N>::S == 2 && sizeof(T) == 4);
-    auto k = k_expand_pipe<N, B, T, MF>;
+    auto k = k_expand_pipe<N, B, T, MF, 0, 0>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sp);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(count * ExpandSplit<N>::S), dim3(B), sp, s, d, c0, (T*)X);
+    hipLaunchKernelGGL(k, grid, dim3(B), sp, s, d, c0, (T*)X, (int*)nullptr, (int*)nullptr);
     return hipGetLastError();
   }
   const size_t sh = sizeof(T) * (N + 3 * N + N + 3 * CS * N + CS * CS * CS + CS * CS * N + 3 * CS * N + 64);
@@ -1237,16 +1277,16 @@ hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixe
   }
   if (mixed) {
     switch (d.N) {
-      case 16: return launch_expand_t<16, float>(d, c0, count, X, s);
-      case 24: return launch_expand_t<24, float>(d, c0, count, X, s);
-      case 32: return launch_expand_t<32, float>(d, c0, count, X, s);
-      case 48: return launch_expand_t<48, float>(d, c0, count, X, s);
+      case 16: return launch_expand_t<16, float>(d, c0, count, X, list, list_n, s);
+      case 24: return launch_expand_t<24, float>(d, c0, count, X, list, list_n, s);
+      case 32: return launch_expand_t<32, float>(d, c0, count, X, list, list_n, s);
+      case 48: return launch_expand_t<48, float>(d, c0, count, X, list, list_n, s);
     }
   } else {
     switch (d.N) {
-      case 16: return launch_expand_t<16, double>(d, c0, count, X, s);
-      case 24: return launch_expand_t<24, double>(d, c0, count, X, s);
-      case 32: return launch_expand_t<32, double>(d, c0, count, X, s);
+      case 16: return launch_expand_t<16, double>(d, c0, count, X, list, list_n, s);
+      case 24: return launch_expand_t<24, double>(d, c0, count, X, list, list_n, s);
+      case 32: return launch_expand_t<32, double>(d, c0, count, X, list, list_n, s);
     }
   }
   return hipErrorInvalidValue;

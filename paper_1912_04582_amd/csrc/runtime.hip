@@ -492,10 +492,10 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     S->X = st_alloc(S, per * 0 + (size_t)S->chunk * N * N * N * tsz, &s);
     if (!S->X) { state_free(S); return s; }
     ALLOC(G, double, (size_t)S->chunk * 3 * N * N);
-    if (oblique) {
-      ALLOC(ob_list, int, (size_t)S->chunk);
-      ALLOC(ob_n, int, 1);
-    }
+    // cells of a pass left to a second expansion launch (oblique faces or
+    // ranks beyond the small LDS layout)
+    ALLOC(ob_list, int, (size_t)S->chunk);
+    ALLOC(ob_n, int, 1);
     if (!S->mixed) ALLOC(Wb, double, (size_t)S->chunk * 3 * N * N);
     ALLOC(Wkeep, double, (size_t)nc * 3 * N * N);
   }

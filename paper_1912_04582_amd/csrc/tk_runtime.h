@@ -95,7 +95,7 @@ struct tk_state {
   // rounding workspaces
   void* X = nullptr;
   double* G = nullptr;
-  int* ob_list = nullptr;  // oblique meshes: cells of a pass left to the general expansion
+  int* ob_list = nullptr;  // cells of a pass left to a second expansion launch
   int* ob_n = nullptr;
   // oblique faces: per-slot outward normal and index of the |xi.e| estimate
   bool oblique = false;

@@ -150,6 +150,33 @@ def small_channel_case(precision="mixed", N=16):
     return m, cfg, synth.initial_macros(cfg, m)
 
 
+def test_expansion_rank_handoff_matches_oracle(ctx):
+    """N = 32, mixed, cap 12 from rough initial fields at tolerance 1e-8:
+    after two steps most cells have ranks above 8, so the third step's
+    expansion runs both launches (sources within the small LDS layout, then
+    the handed-over cells through the full layout); every cell is checked
+    against the FP64 oracle."""
+    m, cfg, m0 = small_channel_case(N=32)
+    cfg = dict(cfg, cap=12, tol=1e-8)
+    mesh = tk.Mesh(ctx, m)
+    st = tk.State(ctx, mesh, cfg, m0)
+    st.step(2)
+    r, _ = st.ranks()
+    print(f"max rank after 2 steps {r.max()}, cells above 8: {(r.max(1) > 8).sum()}", flush=True)
+    assert (r.max(1) > 8).sum() > 10
+    st.step(1)
+    got = st.moments()
+    st.close()
+    mesh.close()
+    S = fv.Setup(m, cfg, m0)
+    n = m["n_cells"]
+    ref = td.run(S, m0, 3)
+    ref = np.array([td.macros_of(S, ref[i]) for i in range(n)])
+    err, _ = macro_rel_err(got, ref)
+    print(f"rank hand-off: max rel macro err {err:.3e}")
+    assert err < 1e-5, err
+
+
 @pytest.mark.parametrize("plain", [False, True])
 def test_checkpoint_restore_continues_bit_for_bit(ctx, plain):
     m, cfg, m0 = small_channel_case()
