@@ -82,14 +82,14 @@ __global__ __launch_bounds__(kProjThreads) void k_project(const T* X, int c0, in
 // reads whole mode-1 fibres (N contiguous values, coalesced across the
 // workgroup) once, Y1 = W1^T A is kept in LDS, then Y2 = Y1 x2 W2^T and
 // C = Y2 x3 W3^T; two barriers in total.  The LDS is laid out for ranks up
-// to `cap` in modes 1 and 2.  A launch takes the cells whose ranks in modes 1
-// and 2 are at most `low_cap` when `take_low` is set, the others otherwise
-// (one launch of each covers every cell once, the first with room for
-// several workgroups per CU).
+// to `cap` in modes 1 and 2.  A launch takes the cells whose larger rank of
+// modes 1 and 2 lies in (lo, hi]; launches over consecutive rank tiers
+// cover every cell once, the low tiers with room for several workgroups per
+// CU.
 template <int N, typename T>
 __global__ __launch_bounds__(kProjThreads) void k_project_fib(const T* X, int c0, int CS, const double* fac_n,
                                                              const int* rank_n, double* core_n, int cap,
-                                                             int low_cap, int take_low) {
+                                                             int lo, int hi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sW = reinterpret_cast<double*>(smem_raw);    // 3 CS N
   double* sY2 = sW + 3 * CS * N;                       // cap cap N
@@ -98,8 +98,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project_fib(const T* X, int c0
   const int cell = c0 + cl;
   const int tid = threadIdx.x;
   const int r1 = rank_n[3 * cell], r2 = rank_n[3 * cell + 1], r3 = rank_n[3 * cell + 2];
-  const bool is_low = r1 <= low_cap && r2 <= low_cap;
-  if (is_low != (take_low != 0)) return;
+  const int r12 = r1 > r2 ? r1 : r2;
+  if (r12 <= lo || r12 > hi) return;
   for (int o = tid; o < 3 * CS * N; o += kProjThreads) sW[o] = fac_n[(size_t)cell * 3 * CS * N + o];
   __syncthreads();
   const T* x = X + (size_t)cl * N * N * N;
@@ -143,8 +143,8 @@ size_t project_fib_bytes(int CS, int cap) {
   return sizeof(double) * (3 * (size_t)CS * N + (size_t)cap * cap * N) + sizeof(T) * (size_t)cap * N * N;
 }
 
-// rank cap of the low-rank projection launch
-constexpr int kProjLowCap = 6;
+// rank tiers of the projection launches: (0, 6], (6, 9], (9, cap]
+constexpr int kProjTier[2] = {6, 9};
 
 template <int N, typename T>
 hipError_t launch_project_t(int count, const void* X, int c0, int CS, const double* fac_n, const int* rank_n,
@@ -152,15 +152,16 @@ hipError_t launch_project_t(int count, const void* X, int c0, int CS, const doub
   const size_t shf = project_fib_bytes<N, T>(CS, CS);
   if (shf <= 96 * 1024) {
     auto k = k_project_fib<N, T>;
-    const int low = CS < kProjLowCap ? CS : kProjLowCap;
-    const size_t shl = project_fib_bytes<N, T>(CS, low);
-    const size_t shmax = shf > shl ? shf : shl;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmax);
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shf);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(count), dim3(kProjThreads), shl, s, (const T*)X, c0, CS, fac_n, rank_n, core_n, low,
-                       low, 1);
-    hipLaunchKernelGGL(k, dim3(count), dim3(kProjThreads), shf, s, (const T*)X, c0, CS, fac_n, rank_n, core_n, CS,
-                       low, 0);
+    int lo = 0;
+    for (int t = 0; t <= 2 && lo < CS; ++t) {
+      const int hi = (t < 2 && kProjTier[t] < CS) ? kProjTier[t] : CS;
+      const size_t sh = project_fib_bytes<N, T>(CS, hi);
+      hipLaunchKernelGGL(k, dim3(count), dim3(kProjThreads), sh, s, (const T*)X, c0, CS, fac_n, rank_n, core_n, hi,
+                         lo, hi);
+      lo = hi;
+    }
     return hipGetLastError();
   }
   const size_t sh = sizeof(double) * (N * N + 3 * CS * N + CS * N + CS * CS);
