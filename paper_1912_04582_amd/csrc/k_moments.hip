@@ -26,28 +26,62 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// sum_k G[k1 + r1 (k2 + r2 k3)] s1[k1] s2[k2] s3[k3], reduced over the wave
-__device__ inline double contract(const double* G, int r1, int r2, int r3, const double* s1,
-                                  const double* s2, const double* s3) {
+// The cell's core, held by the wave: entry o = lane + 64 m in register slot
+// m (with its packed indices) for m < kMomGR, cores beyond that read from
+// global memory.  Keeping it out of LDS leaves room for more cells per CU.
+constexpr int kMomGR = 8;
+
+struct CoreRegs {
+  double g[kMomGR];
+  int k[kMomGR];  // k1 | k2 << 8 | k3 << 16
+  const double* G;  // the cell's core in global memory (layout k1 + CS (k2 + CS k3))
+  int r1, r2, tot, CS;
+};
+
+__device__ inline void core_load(CoreRegs& R, const double* G, int r1, int r2, int r3, int CS) {
+  R.G = G;
+  R.r1 = r1;
+  R.r2 = r2;
+  R.tot = r1 * r2 * r3;
+  R.CS = CS;
+#pragma unroll
+  for (int m = 0; m < kMomGR; ++m) {
+    const int o = threadIdx.x + kMomThreads * m;
+    R.g[m] = 0.0;
+    R.k[m] = 0;
+    if (o < R.tot) {
+      const int k1 = o % r1, t = o / r1, k2 = t % r2, k3 = t / r2;
+      R.g[m] = G[k1 + CS * (k2 + CS * k3)];
+      R.k[m] = k1 | (k2 << 8) | (k3 << 16);
+    }
+  }
+}
+
+// sum_k G[k1, k2, k3] s1[k1] s2[k2] s3[k3] over the core entries in the
+// order o = k1 + r1 (k2 + r2 k3), reduced over the wave
+__device__ inline double contract(const CoreRegs& R, const double* s1, const double* s2, const double* s3) {
   double acc = 0.0;
-  const int tot = r1 * r2 * r3;
-  for (int o = threadIdx.x; o < tot; o += kMomThreads) {
-    const int k1 = o % r1;
-    const int t = o / r1;
-    const int k2 = t % r2;
-    const int k3 = t / r2;
-    acc += G[o] * s1[k1] * s2[k2] * s3[k3];
+#pragma unroll
+  for (int m = 0; m < kMomGR; ++m) {
+    const int o = threadIdx.x + kMomThreads * m;
+    if (o < R.tot) {
+      const int kk = R.k[m];
+      acc += R.g[m] * s1[kk & 255] * s2[(kk >> 8) & 255] * s3[kk >> 16];
+    }
+  }
+  for (int o = threadIdx.x + kMomThreads * kMomGR; o < R.tot; o += kMomThreads) {
+    const int k1 = o % R.r1, t = o / R.r1, k2 = t % R.r2, k3 = t / R.r2;
+    acc += R.G[k1 + R.CS * (k2 + R.CS * k3)] * s1[k1] * s2[k2] * s3[k3];
   }
   return wave_sum(acc);
 }
 
 template <int N>
-__global__ __launch_bounds__(kMomThreads) void k_moments(DevState d) {
+__global__ __launch_bounds__(kMomThreads, 4) void k_moments(DevState d) {
   extern __shared__ double smem[];
   const int CS = d.CS;
   double* sU = smem;                 // [3][CS][N]
-  double* sG = sU + 3 * CS * N;      // [r1 r2 r3]
-  double* sS = sG + CS * CS * CS;    // weighted sums [3][8][CS]
+  double* sS = sU + 3 * CS * N;      // weighted sums [3][8][CS]
   double* sxi = sS + 3 * 8 * CS;     // [N]
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
@@ -58,10 +92,8 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(DevState d) {
   for (int a = 0; a < 3; ++a)
     for (int o = tid; o < rr[a] * N; o += kMomThreads)
       sU[a * CS * N + o] = d.fac[((size_t)c * 3 + a) * CS * N + o];
-  for (int o = tid; o < r1 * r2 * r3; o += kMomThreads) {
-    const int k1 = o % r1, t = o / r1, k2 = t % r2, k3 = t / r2;
-    sG[o] = d.core[(size_t)c * CS * CS * CS + k1 + CS * (k2 + CS * k3)];
-  }
+  CoreRegs sG;
+  core_load(sG, d.core + (size_t)c * CS * CS * CS, r1, r2, r3, CS);
   __syncthreads();
   // raw weighted sums: sS[a][p][k] = dxi * sum_i U_a[k][i] xi_i^p, p = 0, 1, 2
   for (int o = tid; o < 3 * 3 * CS; o += kMomThreads) {
@@ -69,6 +101,7 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(DevState d) {
     double s = 0.0;
     if (k < rr[a]) {
       const double* u = sU + a * CS * N + k * N;
+      #pragma unroll 4
       for (int i = 0; i < N; ++i) {
         const double x = sxi[i];
         s += u[i] * (p == 0 ? 1.0 : (p == 1 ? x : x * x));
@@ -78,11 +111,11 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(DevState d) {
   }
   __syncthreads();
   auto S = [&](int a, int p) { return sS + (a * 8 + p) * CS; };
-  const double n = contract(sG, r1, r2, r3, S(0, 0), S(1, 0), S(2, 0));
+  const double n = contract(sG, S(0, 0), S(1, 0), S(2, 0));
   double u[3];
-  u[0] = contract(sG, r1, r2, r3, S(0, 1), S(1, 0), S(2, 0)) / n;
-  u[1] = contract(sG, r1, r2, r3, S(0, 0), S(1, 1), S(2, 0)) / n;
-  u[2] = contract(sG, r1, r2, r3, S(0, 0), S(1, 0), S(2, 1)) / n;
+  u[0] = contract(sG, S(0, 1), S(1, 0), S(2, 0)) / n;
+  u[1] = contract(sG, S(0, 0), S(1, 1), S(2, 0)) / n;
+  u[2] = contract(sG, S(0, 0), S(1, 0), S(2, 1)) / n;
   __syncthreads();
   // central weighted sums: slots p = 3..5 hold (xi - u_a)^1..3
   for (int o = tid; o < 3 * 3 * CS; o += kMomThreads) {
@@ -90,6 +123,7 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(DevState d) {
     double s = 0.0;
     if (k < rr[a]) {
       const double* uu = sU + a * CS * N + k * N;
+      #pragma unroll 4
       for (int i = 0; i < N; ++i) {
         const double v = sxi[i] - u[a];
         s += uu[i] * (p == 1 ? v : (p == 2 ? v * v : v * v * v));
@@ -99,22 +133,22 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(DevState d) {
   }
   __syncthreads();
   auto C = [&](int a, int p) { return p == 0 ? S(a, 0) : sS + (a * 8 + 2 + p) * CS; };
-  const double c2 = contract(sG, r1, r2, r3, C(0, 2), C(1, 0), C(2, 0)) +
-                    contract(sG, r1, r2, r3, C(0, 0), C(1, 2), C(2, 0)) +
-                    contract(sG, r1, r2, r3, C(0, 0), C(1, 0), C(2, 2));
+  const double c2 = contract(sG, C(0, 2), C(1, 0), C(2, 0)) +
+                    contract(sG, C(0, 0), C(1, 2), C(2, 0)) +
+                    contract(sG, C(0, 0), C(1, 0), C(2, 2));
   const double T = c2 / (3.0 * n * P.Rg);
   double q[3];
   for (int a = 0; a < 3; ++a) {
     const double* w[3];
     for (int b = 0; b < 3; ++b) w[b] = C(b, 0);
     w[a] = C(a, 3);
-    double acc = contract(sG, r1, r2, r3, w[0], w[1], w[2]);
+    double acc = contract(sG, w[0], w[1], w[2]);
     for (int b = 0; b < 3; ++b) {
       if (b == a) continue;
       for (int e = 0; e < 3; ++e) w[e] = C(e, 0);
       w[a] = C(a, 1);
       w[b] = C(b, 2);
-      acc += contract(sG, r1, r2, r3, w[0], w[1], w[2]);
+      acc += contract(sG, w[0], w[1], w[2]);
     }
     q[a] = 0.5 * P.m * acc;
   }
@@ -141,6 +175,7 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(DevState d) {
       double s = 0.0;
       if (k < rr[a]) {
         const double* uu = sU + a * CS * N + k * N;
+        #pragma unroll 4
         for (int i = 0; i < N; ++i) s += uu[i] * fmax(sg * sxi[i], 0.0);
       }
       sw[k] = s;
@@ -148,7 +183,7 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(DevState d) {
     __syncthreads();
     const double* w[3] = {S(0, 0), S(1, 0), S(2, 0)};
     w[a] = sw;
-    const double num = contract(sG, r1, r2, r3, w[0], w[1], w[2]) / P.dxi / P.dxi;
+    const double num = contract(sG, w[0], w[1], w[2]) / P.dxi / P.dxi;
     const double* fw = d.bc_fac + (size_t)d.slot_nb[kSlots * c + l] * 3 * N;
     double den = 1.0;
     for (int b = 0; b < 3; ++b) {
@@ -193,7 +228,7 @@ hipError_t launch_init_maxwell(const DevState& d, const double* macro5, hipStrea
 
 hipError_t launch_moments(const DevState& d, hipStream_t s) {
   if (d.n_cells == 0) return hipSuccess;
-  const size_t sh = sizeof(double) * (3 * d.CS * d.N + d.CS * d.CS * d.CS + 3 * 8 * d.CS + d.N);
+  const size_t sh = sizeof(double) * (3 * d.CS * d.N + 3 * 8 * d.CS + d.N);
   switch (d.N) {
     case 16: hipLaunchKernelGGL(k_moments<16>, dim3(d.n_cells), dim3(kMomThreads), sh, s, d); break;
     case 24: hipLaunchKernelGGL(k_moments<24>, dim3(d.n_cells), dim3(kMomThreads), sh, s, d); break;
