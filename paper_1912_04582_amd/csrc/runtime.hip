@@ -68,7 +68,7 @@ void ctx_free(tk_ctx* ctx, void* p) {
   (void)hipFree(p);
 }
 
-void prof_begin(tk_ctx* ctx, int kid, hipEvent_t* ev) {
+void prof_begin(tk_ctx* ctx, int kid, hipEvent_t* ev, hipStream_t q = nullptr) {
   *ev = nullptr;
   if (!ctx->prof) return;
   if (ctx->ev_pool.empty()) {
@@ -78,11 +78,11 @@ void prof_begin(tk_ctx* ctx, int kid, hipEvent_t* ev) {
   }
   *ev = ctx->ev_pool.back();
   ctx->ev_pool.pop_back();
-  (void)hipEventRecord(*ev, ctx->stream);
+  (void)hipEventRecord(*ev, q ? q : ctx->stream);
   (void)kid;
 }
 
-void prof_end(tk_ctx* ctx, int kid, hipEvent_t start) {
+void prof_end(tk_ctx* ctx, int kid, hipEvent_t start, hipStream_t q = nullptr) {
   if (!ctx->prof || !start) return;
   hipEvent_t e;
   if (ctx->ev_pool.empty()) {
@@ -91,7 +91,7 @@ void prof_end(tk_ctx* ctx, int kid, hipEvent_t start) {
     e = ctx->ev_pool.back();
     ctx->ev_pool.pop_back();
   }
-  (void)hipEventRecord(e, ctx->stream);
+  (void)hipEventRecord(e, q ? q : ctx->stream);
   ctx->pending.push_back({kid, start, e});
 }
 
@@ -231,6 +231,11 @@ void state_free(tk_state* st) {
   st->gexec[0] = st->gexec[1] = nullptr;
   for (hipEvent_t e : st->tune_ev) (void)hipEventDestroy(e);
   st->tune_ev.clear();
+  if (st->ev_fork) (void)hipEventDestroy(st->ev_fork);
+  if (st->ev_join) (void)hipEventDestroy(st->ev_join);
+  if (st->q2) (void)hipStreamDestroy(st->q2);
+  st->ev_fork = st->ev_join = nullptr;
+  st->q2 = nullptr;
   for (void* p : st->allocs) ctx_free(ctx, p);
   st->allocs.clear();
 }
@@ -498,6 +503,27 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     ALLOC(ob_n, int, 1);
     if (!S->mixed) ALLOC(Wb, double, (size_t)S->chunk * 3 * N * N);
     ALLOC(Wkeep, double, (size_t)nc * 3 * N * N);
+    // optional second workspace: only if it fits what the budget leaves
+    // (with a margin), so that no error is recorded when it does not
+    const size_t ch = (size_t)S->chunk;
+    const size_t need = ch * N * N * N * tsz + ch * 3 * N * N * 8 * (S->mixed ? 1 : 2) + ch * 4 + 4096;
+    if (nc > 1 && ctx->used + need + (64u << 20) <= ctx->budget) {
+      tk_status s2 = TK_OK;
+      S->X2 = st_alloc(S, ch * N * N * N * tsz, &s2);
+      if (S->X2) S->G2 = (double*)st_alloc(S, ch * 3 * N * N * 8, &s2);
+      if (S->G2 && !S->mixed) S->Wb2 = (double*)st_alloc(S, ch * 3 * N * N * 8, &s2);
+      if (S->G2 && (S->mixed || S->Wb2)) S->ob_list2 = (int*)st_alloc(S, ch * 4, &s2);
+      if (S->ob_list2) S->ob_n2 = (int*)st_alloc(S, 4, &s2);
+      if (S->ob_n2 && hipStreamCreate(&S->q2) != hipSuccess) S->q2 = nullptr;
+      if (S->q2 && (hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                    hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming) != hipSuccess)) {
+        if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
+        S->ev_fork = nullptr;
+        (void)hipStreamDestroy(S->q2);
+        S->q2 = nullptr;
+      }
+      if (!S->q2) S->X2 = nullptr;  // the pieces are released with the state
+    }
   }
 #undef ALLOC
   hipStream_t q = ctx->stream;
@@ -653,35 +679,58 @@ static tk_status state_step_once(tk_state* st) {
   e = launch_moments(d, q);
   prof_end(ctx, KID_MOMENTS, ev);
   if (e != hipSuccess) return ctx_hip(ctx, e, "moments");
-  for (int c0 = 0; c0 < st->nc; c0 += st->chunk) {
+  // odd passes on the second stream with the second workspace: the passes
+  // are independent (each reads the current state and writes its own cells
+  // of the next one), and a stream reuses its workspace only after its
+  // previous pass
+  const bool dual = st->X2 && st->q2 && !st->capturing;
+  if (dual) {
+    e = hipEventRecord(st->ev_fork, q);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st->q2, st->ev_fork, 0);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "fork");
+  }
+  int pass = 0;
+  for (int c0 = 0; c0 < st->nc; c0 += st->chunk, ++pass) {
     const int cnt = std::min(st->chunk, st->nc - c0);
-    prof_begin(ctx, KID_EXPAND, &ev);
-    e = launch_expand(d, c0, cnt, st->X, st->mixed, st->oblique ? 1 : 0, st->ob_list, st->ob_n, q);
-    prof_end(ctx, KID_EXPAND, ev);
+    const bool two = dual && (pass & 1);
+    hipStream_t sq = two ? st->q2 : q;
+    void* X = two ? st->X2 : st->X;
+    double* G = two ? st->G2 : st->G;
+    double* Wb = two ? st->Wb2 : st->Wb;
+    int* obl = two ? st->ob_list2 : st->ob_list;
+    int* obn = two ? st->ob_n2 : st->ob_n;
+    prof_begin(ctx, KID_EXPAND, &ev, sq);
+    e = launch_expand(d, c0, cnt, X, st->mixed, st->oblique ? 1 : 0, obl, obn, sq);
+    prof_end(ctx, KID_EXPAND, ev, sq);
     if (e != hipSuccess) return ctx_hip(ctx, e, "expand");
-    prof_begin(ctx, KID_GRAM, &ev);
-    e = launch_gram(st->N, cnt, st->X, st->mixed, st->G, q);
-    prof_end(ctx, KID_GRAM, ev);
+    prof_begin(ctx, KID_GRAM, &ev, sq);
+    e = launch_gram(st->N, cnt, X, st->mixed, G, sq);
+    prof_end(ctx, KID_GRAM, ev, sq);
     if (e != hipSuccess) return ctx_hip(ctx, e, "gram");
-    prof_begin(ctx, KID_EIG, &ev);
+    prof_begin(ctx, KID_EIG, &ev, sq);
     if (st->mixed) {
-      e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
-                     nullptr, st->Wkeep, 1e-12, 1e-15, q, 0.0, st->warm ? d.rank : nullptr, st->warm ? 6 : 0);
+      e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
+                     nullptr, st->Wkeep, 1e-12, 1e-15, sq, 0.0, st->warm ? d.rank : nullptr, st->warm ? 6 : 0);
     } else {
       // FP64 path: first basis, Gram of the rotated unfoldings, final basis
-      e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
-                     st->Wb, st->Wkeep, 1e-15, 1e-18, q);
-      if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, st->X, 0, st->Wb, st->G, q);
+      e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr, Wb,
+                     st->Wkeep, 1e-15, 1e-18, sq);
+      if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, X, 0, Wb, G, sq);
       if (e == hipSuccess)
-        e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, st->Wb,
-                       nullptr, nullptr, 1e-15, 1e-18, q);
+        e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, Wb, nullptr,
+                       nullptr, 1e-15, 1e-18, sq);
     }
-    prof_end(ctx, KID_EIG, ev);
+    prof_end(ctx, KID_EIG, ev, sq);
     if (e != hipSuccess) return ctx_hip(ctx, e, "eig");
-    prof_begin(ctx, KID_PROJECT, &ev);
-    e = launch_project(st->N, cnt, st->X, st->mixed, c0, st->CS, d.fac_n, d.rank_n, d.core_n, q);
-    prof_end(ctx, KID_PROJECT, ev);
+    prof_begin(ctx, KID_PROJECT, &ev, sq);
+    e = launch_project(st->N, cnt, X, st->mixed, c0, st->CS, d.fac_n, d.rank_n, d.core_n, sq);
+    prof_end(ctx, KID_PROJECT, ev, sq);
     if (e != hipSuccess) return ctx_hip(ctx, e, "project");
+  }
+  if (dual) {
+    e = hipEventRecord(st->ev_join, st->q2);
+    if (e == hipSuccess) e = hipStreamWaitEvent(q, st->ev_join, 0);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "join");
   }
   st->cur ^= 1;
   st->warm = true;
@@ -700,7 +749,9 @@ static tk_status state_step_graph(tk_state* st) {
     hipGraph_t g = nullptr;
     e = hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return ctx_hip(ctx, e, "graph capture");
+    st->capturing = true;  // one stream inside the graph
     const tk_status s = state_step_once(st);
+    st->capturing = false;
     e = hipStreamEndCapture(q, &g);
     st->cur = p;
     if (s != TK_OK) {

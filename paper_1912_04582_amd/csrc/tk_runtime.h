@@ -97,6 +97,17 @@ struct tk_state {
   double* G = nullptr;
   int* ob_list = nullptr;  // cells of a pass left to a second expansion launch
   int* ob_n = nullptr;
+  // second workspace and stream: odd passes of a step run there, so one
+  // pass's eigensolves overlap the next pass's expansion (allocated only
+  // when the budget leaves room; not used while timing kernels or capturing)
+  void* X2 = nullptr;
+  double* G2 = nullptr;
+  double* Wb2 = nullptr;
+  int* ob_list2 = nullptr;
+  int* ob_n2 = nullptr;
+  hipStream_t q2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool capturing = false;
   // oblique faces: per-slot outward normal and index of the |xi.e| estimate
   bool oblique = false;
   int n_est = 0;
