@@ -626,7 +626,8 @@ constexpr int kTuneReps = 3;
 
 static std::vector<int> chunk_candidates(const tk_state* st) {
   const size_t x = (size_t)st->N * st->N * st->N * (st->mixed ? 4 : 8);
-  std::vector<int> c = {st->chunk_max, 16384, 8192, 4096, 2048, (int)std::max<size_t>(256, (192u << 20) / x)};
+  std::vector<int> c = {st->chunk_max, 16384, 12288, 8192, 6144, 4096, 2048,
+                        (int)std::max<size_t>(256, (192u << 20) / x)};
   std::vector<int> out;
   for (int v : c)
     if (v <= st->chunk_max && v >= 256 && std::find(out.begin(), out.end(), v) == out.end()) out.push_back(v);
