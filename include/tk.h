@@ -128,8 +128,10 @@ tk_status tk_ctx_create(int32_t device, size_t hbm_budget, void* hip_stream, tk_
 tk_status tk_ctx_destroy(tk_ctx* ctx);
 const char* tk_last_error(const tk_ctx* ctx);
 tk_status tk_sync(tk_ctx* ctx);
-/* Per-kernel timing with HIP events recorded on the context stream around
- * every launch of the named kernel family while enabled.                  */
+/* Per-kernel timing with HIP events recorded around every launch of the
+ * named kernel family while enabled, on the stream the launch runs on (the
+ * context stream, or the state's second stream for alternate rounding
+ * passes: then a launch's time includes the concurrent pass's kernels).  */
 tk_status tk_prof_enable(tk_ctx* ctx, int32_t on);
 tk_status tk_prof_get(tk_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
 tk_status tk_prof_reset(tk_ctx* ctx);
@@ -202,7 +204,12 @@ tk_status tk_state_restore(tk_state* st, const void* buf, size_t bytes);
 tk_status tk_moments(tk_state* st, double* out);
 
 /* Advance nsteps explicit steps (Alg. 1 with one rounding per cell per
- * step).  Enqueued on the context stream and waited for.  residual, if not
+ * step).  Enqueued on the context stream and waited for.  When the budget
+ * left room for a second workspace at tk_state_init, alternate rounding
+ * passes of a step run on a second stream of the state's own, forked from
+ * and joined back into the context stream within the step, with the same
+ * results; to the caller a step remains ordered work on the context
+ * stream.  residual, if not
  * NULL, receives per instance max(||dn||/||n||, ||dT||/||T||) over the
  * last step (cell-volume weighted 2-norms).  TK_ENUMERIC if a cell's n or
  * T became non-positive or non-finite (the state is left as computed).    */
