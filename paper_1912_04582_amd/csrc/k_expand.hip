@@ -339,26 +339,52 @@ __device__ inline void src_store(const DevState& d, const InstParams& P, const E
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 
+// Orders the LDS accesses of one wavefront's lanes (a wave's LDS
+// instructions execute in order; this keeps the compiler from moving them
+// across the point).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Y = G x3 U3 of one staged source at the wave's two i3 (i3a, i3a + 1), all
+// j < r1, k2 < r2, into the wave's own LDS slice wy[(j r2 + k2) 2 + t]
+// (the same sums, in the same order, as y_stage); no workgroup barrier.
+__device__ inline void wave_y(const float* sU, const float* sG, float* wy, int r1, int r2, int r3, int LS, int lane,
+                              int i3a) {
+  constexpr int N = 32;
+  const float* U3 = sU + 2 * LS * N;
+  const int E = 2 * r1 * r2;
+  for (int o = lane; o < E; o += 64) {
+    const int t = o & 1, jk = o >> 1, k2 = jk % r2, j = jk / r2;
+    float sacc = 0.f;
+    const float* g = sG + j + r1 * k2;
+    for (int k3 = 0; k3 < r3; ++k3) sacc += g[r1 * r2 * k3] * U3[k3 * N + i3a + t];
+    wy[o] = sacc;
+  }
+}
+
 // Last two mode products of one source on the matrix cores (N = 32, FP32):
 // for the wave's tiles X[i1, i2, i3] (i3 = i3a, i3a + 1; all i1, i2),
 //   X^T[i2, i1] += sum_j Z_j[i2, i3] U1[i1, j],  Z_j = U2 Y_j,
 // two values of j per v_mfma_f32_32x32x2f32.  Lane l supplies the A value
 // at row l % 32, k = l / 32 (z of j = j0 + l / 32 at i2 = l % 32, formed by
-// the lane itself) and the B value at k = l / 32, column l % 32 (U1[l % 32,
-// j]); it holds D rows 8 (v / 4) + 4 (l / 32) + v % 4 of column l % 32.
-__device__ inline void tile_products(v16f& t0, v16f& t1, const float* sU, const float* sY, int r1, int r2, int CS,
-                                     int li, int hi, int i3a) {
+// the lane itself from the wave's Y slice) and the B value at k = l / 32,
+// column l % 32 (U1[l % 32, j]); it holds D rows 8 (v / 4) + 4 (l / 32) +
+// v % 4 of column l % 32.
+__device__ inline void tile_products(v16f& t0, v16f& t1, const float* sU, const float* wy, int r1, int r2, int LS,
+                                     int li, int hi) {
   constexpr int N = 32;
   const float* U1 = sU;
-  const float* U2 = sU + CS * N;
+  const float* U2 = sU + LS * N;
   for (int j0 = 0; j0 < r1; j0 += 2) {
     const int j = j0 + hi;
     float z0 = 0.f, z1 = 0.f, u1 = 0.f;
     if (j < r1) {
-      const float* y = sY + j * r2 * N + i3a;
+      const float* y = wy + 2 * j * r2;
       for (int k2 = 0; k2 < r2; ++k2) {
         const float u2 = U2[k2 * N + li];
-        const float2 yy = *reinterpret_cast<const float2*>(y + k2 * N);
+        const float2 yy = *reinterpret_cast<const float2*>(y + 2 * k2);
         z0 += u2 * yy.x;
         z1 += u2 * yy.y;
       }
@@ -387,11 +413,12 @@ __global__ __launch_bounds__(BLOCK, RB > 0 ? 6 : 1) void k_expand_pipe(DevState 
   T* smem = reinterpret_cast<T*>(smem_raw);
   const int LS = RB > 0 ? RB : d.CS;                     // rank extent of the LDS layout
   const int GS = (LS * LS * LS + 1) & ~1;                // core extent, even so Y stays 8-byte aligned
-  const int BUF = 3 * LS * N + GS + LS * LS * N;         // sU, sG, sY of one buffer
+  const int BUF = 3 * LS * N + GS + (MF ? 0 : LS * LS * N);  // sU, sG (and sY) of one buffer
   T* sd = smem;                   // 3 N   own-cell outflow tables d_a
   T* sFU = sd + 3 * N;            // 3 LS N   f_S factors
   T* sFG = sFU + 3 * LS * N;      // 64       f_S core
   T* sB = sFG + 64;               // two buffers
+  T* sWY = sB + 2 * BUF;          // MF: per wave 2 LS LS values of Y
   const int part = blockIdx.x % SPLIT;
   int cb = blockIdx.x / SPLIT;
   if constexpr (LIST == 2) {
@@ -529,9 +556,10 @@ __global__ __launch_bounds__(BLOCK, RB > 0 ? 6 : 1) void k_expand_pipe(DevState 
   }
   src_store<N, BLOCK, T>(d, P, s_src[0], pre, sB, sB + 3 * LS * N, LS);
   __syncthreads();
-  y_stage<N, BLOCK, T>(sB, sB + 3 * LS * N, sB + 3 * LS * N + GS, s_src[0].q1, s_src[0].q2, s_src[0].q3,
-                       LS);
-  __syncthreads();
+  if constexpr (!MF) {
+    y_stage<N, BLOCK, T>(sB, sB + 3 * LS * N, sB + 3 * LS * N + GS, s_src[0].q1, s_src[0].q2, s_src[0].q3, LS);
+    __syncthreads();
+  }
 
   // VALU path: whole mode-1 fibres per thread.  MFMA path (MF): each wave
   // owns the 32 x 32 tiles (i2 x i1) of two consecutive i3.
@@ -558,7 +586,13 @@ __global__ __launch_bounds__(BLOCK, RB > 0 ? 6 : 1) void k_expand_pipe(DevState 
     const T* su = e.type == SRC_FS ? sFU : cur;
     const T* sy = cur + 3 * LS * N + GS;
     if constexpr (MF) {
-      tile_products(t0, t1, (const float*)su, (const float*)sy, e.q1, e.q2, LS, li, hi, i3a);
+      float* wy = reinterpret_cast<float*>(sWY) + (tid >> 6) * 2 * LS * LS;
+      if (e.type == SRC_FS)
+        wave_y((const float*)sFU, (const float*)sFG, wy, 4, 4, 4, LS, lane, i3a);
+      else
+        wave_y((const float*)cur, (const float*)(cur + 3 * LS * N), wy, e.q1, e.q2, e.q3, LS, lane, i3a);
+      wave_sync();
+      tile_products(t0, t1, (const float*)su, wy, e.q1, e.q2, LS, li, hi);
     } else {
       fibre_products<N, T, FIB>(acc, su, sy, e.q1, e.q2, LS, pf);
     }
@@ -588,11 +622,13 @@ __global__ __launch_bounds__(BLOCK, RB > 0 ? 6 : 1) void k_expand_pipe(DevState 
       const ExpSrc& en = s_src[sidx + 1];
       src_store<N, BLOCK, T>(d, P, en, pre, nxt, nxt + 3 * LS * N, LS);
       __syncthreads();
-      if (en.type == SRC_FS)
-        y_stage<N, BLOCK, T>(sFU, sFG, nxt + 3 * LS * N + GS, 4, 4, 4, LS);
-      else
-        y_stage<N, BLOCK, T>(nxt, nxt + 3 * LS * N, nxt + 3 * LS * N + GS, en.q1, en.q2, en.q3, LS);
-      __syncthreads();
+      if constexpr (!MF) {
+        if (en.type == SRC_FS)
+          y_stage<N, BLOCK, T>(sFU, sFG, nxt + 3 * LS * N + GS, 4, 4, 4, LS);
+        else
+          y_stage<N, BLOCK, T>(nxt, nxt + 3 * LS * N, nxt + 3 * LS * N + GS, en.q1, en.q2, en.q3, LS);
+        __syncthreads();
+      }
     }
   }
 
@@ -1217,26 +1253,31 @@ template <int N, typename T>
 hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, int* list, int* list_n, hipStream_t s) {
   constexpr int B = ExpandShape<N>::B;
   const int CS = d.CS;
-  const size_t buf = 3 * CS * N + ((CS * CS * CS + 1) & ~1) + CS * CS * N;
-  const size_t sp = sizeof(T) * (3 * N + 3 * CS * N + 64 + 2 * buf);
   constexpr bool MF = (N == 32 && B == 512 && ExpandSplit<N>::S == 2 && sizeof(T) == 4);
   const dim3 grid(count * ExpandSplit<N>::S);
+  // LDS of k_expand_pipe for rank extent LS: tables, f_S, two buffers and,
+  // on the MFMA path, each wave's Y slice instead of a shared Y
+  auto pipe_lds = [&](int LS) -> size_t {
+    const size_t b = 3 * LS * N + ((LS * LS * LS + 1) & ~1) + (MF ? 0 : LS * LS * N);
+    return sizeof(T) * (3 * N + 3 * LS * N + 64 + 2 * b + (MF ? (B / 64) * 2 * LS * LS : 0));
+  };
   if (MF && CS > kExpRB && list && list_n) {
     // cells whose sources all have ranks <= kExpRB: a small LDS layout, three
     // workgroups per CU; the rest through the full layout, from the list
     constexpr int RB = kExpRB;
-    const size_t bufs = 3 * RB * N + ((RB * RB * RB + 1) & ~1) + RB * RB * N;
-    const size_t ss = sizeof(T) * (3 * N + 3 * RB * N + 64 + 2 * bufs);
+    const size_t ss = pipe_lds(RB);
+    const size_t sl = pipe_lds(CS);
     auto kf = k_expand_pipe<N, B, T, MF, RB, 1>;
     auto kl = k_expand_pipe<N, B, T, MF, 0, 2>;
     hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ss);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)kl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sp);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)kl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sl);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, list_n);
     hipLaunchKernelGGL(kf, grid, dim3(B), ss, s, d, c0, (T*)X, list, list_n);
-    hipLaunchKernelGGL(kl, grid, dim3(B), sp, s, d, c0, (T*)X, list, list_n);
+    hipLaunchKernelGGL(kl, grid, dim3(B), sl, s, d, c0, (T*)X, list, list_n);
     return hipGetLastError();
   }
+  const size_t sp = pipe_lds(CS);
   if (sp <= 80 * 1024) {
     // two buffers still leave room for two workgroups per CU
     auto k = k_expand_pipe<N, B, T, MF, 0, 0>;
