@@ -410,7 +410,7 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "launches": 5}))
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU per process: the step runs on a single device; --gpus must be 1"}))
         sys.exit(2)
     if a.workload == "serve":
         r = run_serve(a.serve_count, a.serve_max_steps)

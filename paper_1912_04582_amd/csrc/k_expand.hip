@@ -14,8 +14,9 @@
 // where g_l is the neighbour's Tucker state or the boundary ghost.  Every
 // source (the cell, f_S, the six far sides) is expanded from its Tucker
 // form by three mode products, G x3 U3 -> x2 U2 -> x1 U1, staged through
-// LDS in chunks of the first rank index; the last product accumulates
-// straight into registers: each thread owns whole mode-1 fibres of f*.
+// LDS; the last product accumulates straight into registers: in the fibre
+// form each thread owns whole mode-1 fibres of f*, in the matrix-core form
+// (k_expand_pipe at N = 32, FP32) each wave owns 32 x 32 tiles.
 // f_S is built directly in Tucker form with mode ranks 4: columns
 // m_a(xi) (xi - u_a)^k, k = 0..3, and a 4x4x4 core with 13 non-zeros
 // (the expansion of f_M [1 + A_s (q.v)(v^2/(2 R_g T) - 5/2)]).
