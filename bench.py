@@ -207,7 +207,7 @@ def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True):
         w = tk.State(ctx, tm, cfg, m0, plain=plain)
         trials = w.tune()
         if not plain:
-            log(f"  rounding pass: {w.chunk()[0]} cells (of {w.chunk()[1]}), chosen over {trials} steps (16 untimed, then 3 per size)")
+            log(f"  rounding pass: {w.chunk()[0]} cells (of {w.chunk()[1]}), chosen over {trials} steps (16 untimed, then 4 per size)")
         if warmup:
             w.step(warmup)
         w.close()

@@ -166,9 +166,10 @@ tk_status tk_state_dt(const tk_state* st, int32_t inst, double* dt);
 /* Cells per rounding pass (the expansion workspace holds one pass).
  * cells = 0 lets the library choose: on the first state of a shape (N,
  * precision, rank cap, cell count, face kind) on a context, 16 ordinary
- * steps (so that the ranks resemble a running state) are followed by 3
- * timed steps with each of several pass sizes, and the fastest size is
- * kept for every later state of that shape on the context.  cells > 0 fixes the pass size
+ * steps (so that the ranks resemble a running state) are followed by 4
+ * timed steps with each of several pass sizes (cycles over the sizes in
+ * alternating order), and the size with the smallest mean time is kept
+ * for every later state of that shape on the context.  cells > 0 fixes the pass size
  * (TK_EINVAL above the allocated maximum).  Every choice computes the same
  * bits: cells are independent within a pass.  tk_state_chunk reports the
  * size in use and the allocated maximum.                                  */

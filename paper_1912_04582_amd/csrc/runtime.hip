@@ -619,10 +619,18 @@ static std::string tune_key(const tk_state* st) {
 // cache rather than HBM).
 // Pass-size trials: ordinary steps first, so that the ranks (and with them
 // the cost of every kernel) resemble a running state rather than the
-// rank-1 start, then kTuneReps timed steps per candidate, the fastest of
-// them counted.
+// rank-1 start, then kTuneReps timed steps per candidate in cycles over the
+// candidates, alternately in ascending and descending order, compared by
+// their mean: step costs still drift as ranks grow, and the alternation
+// gives every candidate the same mean position in the sequence.
 constexpr int kTuneSkip = 16;
-constexpr int kTuneReps = 3;
+constexpr int kTuneReps = 4;
+
+// candidate index of trial step t (nc candidates)
+static int tune_index(int t, int nc) {
+  const int cyc = t / nc, pos = t % nc;
+  return (cyc & 1) ? nc - 1 - pos : pos;
+}
 
 static std::vector<int> chunk_candidates(const tk_state* st) {
   const size_t x = (size_t)st->N * st->N * st->N * (st->mixed ? 4 : 8);
@@ -780,7 +788,7 @@ static tk_status state_step(tk_state* st) {
   }
   if (st->tune == 1) {
     const int nc = (int)st->tune_cand.size();
-    st->chunk = st->tune_cand[st->tune_step % nc];
+    st->chunk = st->tune_cand[tune_index(st->tune_step, nc)];
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return ctx_fail(ctx, TK_EDEVICE, "event");
     if (hipEventCreate(&b) != hipSuccess) {
@@ -794,13 +802,13 @@ static tk_status state_step(tk_state* st) {
     (void)hipEventRecord(b, ctx->stream);
     if (s != TK_OK) return s;
     if (++st->tune_step == kTuneReps * nc) {
-      // the smallest of the timings per candidate
-      std::vector<float> best(nc, 1e30f);
+      // the mean of the timings per candidate
+      std::vector<float> best(nc, 0.f);
       hipError_t e = hipEventSynchronize(b);
       for (int k = 0; e == hipSuccess && k < kTuneReps * nc; ++k) {
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, st->tune_ev[2 * k], st->tune_ev[2 * k + 1]);
-        best[k % nc] = std::min(best[k % nc], ms);
+        best[tune_index(k, nc)] += ms;
       }
       tune_events_free(st);
       st->tune = 0;

@@ -107,8 +107,8 @@ def test_pass_size_choice_is_kept_per_shape():
         a = tk.State(c, mesh, cfg, m0)
         _, cmax = a.chunk()
         trials = a.tune()
-        # 16 untimed steps, then 3 timed steps per candidate size
-        assert trials >= 16 + 3 * 2 and (trials - 16) % 3 == 0
+        # 16 untimed steps, then 4 timed steps per candidate size
+        assert trials >= 16 + 4 * 2 and (trials - 16) % 4 == 0
         chosen, _ = a.chunk()
         assert 256 <= chosen <= cmax
         assert a.tune() == 0
