@@ -198,13 +198,15 @@ def macro_rel_err(a, b, Rg=0.5, m=1.0):
     return float(e)
 
 
-def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True):
+def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True, one_stream=False):
     ctx = tk.Context(0)
     try:
         tm = tk.Mesh(ctx, mesh)
         # untimed: the pass-size trial steps (the choice is kept on the
         # context for the timed state of the same shape), then the warm-up
         w = tk.State(ctx, tm, cfg, m0, plain=plain)
+        if one_stream and not plain:
+            w.streams(False)
         trials = w.tune()
         if not plain:
             log(f"  rounding pass: {w.chunk()[0]} cells (of {w.chunk()[1]}), chosen over {trials} steps (16 untimed, then 4 per size)")
@@ -212,6 +214,8 @@ def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True):
             w.step(warmup)
         w.close()
         st = tk.State(ctx, tm, cfg, m0, plain=plain)
+        if one_stream and not plain:
+            st.streams(False)
         ctx.sync()
         ctx.prof_reset()
         ctx.prof_enable(prof)
@@ -380,6 +384,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="run every rounding pass on one stream (per-kernel times without the concurrent pass)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--parity-steps", type=int, default=None,
@@ -470,7 +476,7 @@ def main():
     if a.parity_cells is None:
         a.parity_cells = 4 if oblique else 24
     log(f"workload {cfg['name']}: {nc} cells, N={N}, cap {cfg['cap']}, tol {cfg['tol']}, {cfg['precision']}")
-    res = run_gpu(cfg, mesh, m0, a.steps, a.warmup)
+    res = run_gpu(cfg, mesh, m0, a.steps, a.warmup, one_stream=a.one_stream)
     ms_step = 1e3 * res["seconds"] / a.steps
     value = nc * a.steps / res["seconds"]
     log(f"tucker: {ms_step:.2f} ms/step, {value:.4g} cell-updates/s, mean compression {res['compression']:.4g}")
@@ -536,7 +542,8 @@ def main():
         "dtype": "f32 terms + f64 rounding" if cfg["precision"] == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "cells": nc, "N": N, "rank_cap": cfg["cap"], "tol": cfg["tol"],
-                   "precision": cfg["precision"], "steps_from_init": a.steps},
+                   "precision": cfg["precision"], "steps_from_init": a.steps,
+                   "rounding_streams": 1 if a.one_stream else 2},
         "dominant_kernel": fam,
         "kernel_ms_per_step": {f: ms / a.steps for f, (ms, n) in res["prof"].items()},
         "mean_compression": res["compression"],

@@ -184,6 +184,12 @@ tk_status tk_state_tune(tk_state* st, int32_t* steps_run);
  * again when the pass size changes); not while kernel timing is enabled.
  * The results are those of the eager launches.                           */
 tk_status tk_state_use_graph(tk_state* st, int32_t on);
+/* two = 1: alternate rounding passes on the state's second stream (the
+ * default when its second workspace was allocated); two = 0: every pass on
+ * the context stream (for timing kernels one at a time); two < 0: leave
+ * the setting.  available (nullable) receives 1 if the second workspace
+ * and stream exist.  Results are the same either way.                    */
+tk_status tk_state_streams(tk_state* st, int32_t two, int32_t* available);
 
 /* Restart checkpoints (Sec. "The program": a run is continued from a saved
  * solution).  tk_state_checkpoint writes the whole state to host memory:

@@ -692,7 +692,7 @@ static tk_status state_step_once(tk_state* st) {
   // are independent (each reads the current state and writes its own cells
   // of the next one), and a stream reuses its workspace only after its
   // previous pass
-  const bool dual = st->X2 && st->q2 && !st->capturing;
+  const bool dual = st->X2 && st->q2 && !st->capturing && !st->one_stream;
   if (dual) {
     e = hipEventRecord(st->ev_fork, q);
     if (e == hipSuccess) e = hipStreamWaitEvent(st->q2, st->ev_fork, 0);
@@ -1210,6 +1210,15 @@ tk_status tk_state_use_graph(tk_state* st, int32_t on) {
   if (!st) return TK_EINVAL;
   std::lock_guard<std::recursive_mutex> g(st->ctx->mu);
   st->use_graph = on != 0;
+  return TK_OK;
+}
+
+tk_status tk_state_streams(tk_state* st, int32_t two, int32_t* available) {
+  if (!st) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(st->ctx->mu);
+  const bool have = st->X2 && st->q2;
+  if (available) *available = have ? 1 : 0;
+  if (two >= 0) st->one_stream = two == 0;
   return TK_OK;
 }
 

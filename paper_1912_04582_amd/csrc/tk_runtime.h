@@ -108,6 +108,7 @@ struct tk_state {
   hipStream_t q2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool capturing = false;
+  bool one_stream = false;  // tk_state_streams(st, 0): all passes on the context stream
   // oblique faces: per-slot outward normal and index of the |xi.e| estimate
   bool oblique = false;
   int n_est = 0;

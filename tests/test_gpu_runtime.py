@@ -52,25 +52,27 @@ def test_pass_sizes_give_identical_bits(ctx):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_two_stream_passes_give_identical_bits(precision):
-    """Several rounding passes run alternately on two streams with two
-    workspaces (kernel timing on, events on each pass's stream); one pass
-    over all cells uses one.  Both must give the same bits."""
+    """Rounding passes alternating between two streams with two workspaces
+    (kernel timing on, events on each pass's stream), all passes on one
+    stream, and one pass over every cell must give the same bits."""
     c = tk.Context(0)
     try:
         m, cfg, m0 = box_case(8, N=16, precision=precision)
         mesh = tk.Mesh(c, m)
         out = []
-        for chunk in (None, 100):  # one pass; 6 passes, the last ragged
+        for chunk, two in ((None, True), (100, True), (100, False)):  # 6 passes, the last ragged
             st = tk.State(c, mesh, cfg, m0)
+            assert st.streams(two)
             st.set_chunk(chunk or st.chunk()[1])
             c.prof_enable(True)
             st.step(3)
             c.prof_enable(False)
             out.append((st.moments(), st.ranks()[0], st.export(77, cfg["N"])))
             st.close()
-        (ma, ra, (ga, ua)), (mb, rb, (gb, ub)) = out
-        assert np.array_equal(ma, mb) and np.array_equal(ra, rb)
-        assert np.array_equal(ga, gb) and all(np.array_equal(x, y) for x, y in zip(ua, ub))
+        ma, ra, (ga, ua) = out[0]
+        for mb, rb, (gb, ub) in out[1:]:
+            assert np.array_equal(ma, mb) and np.array_equal(ra, rb)
+            assert np.array_equal(ga, gb) and all(np.array_equal(x, y) for x, y in zip(ua, ub))
         mesh.close()
     finally:
         c.close()
