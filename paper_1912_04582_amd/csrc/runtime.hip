@@ -698,6 +698,12 @@ static tk_status state_step_once(tk_state* st) {
     if (e == hipSuccess) e = hipStreamWaitEvent(st->q2, st->ev_fork, 0);
     if (e != hipSuccess) return ctx_hip(ctx, e, "fork");
   }
+  // on an error, order the second stream's work before later context-stream
+  // work all the same
+  auto fail = [&](const char* what) -> tk_status {
+    if (dual && hipEventRecord(st->ev_join, st->q2) == hipSuccess) (void)hipStreamWaitEvent(q, st->ev_join, 0);
+    return ctx_hip(ctx, e, what);
+  };
   int pass = 0;
   for (int c0 = 0; c0 < st->nc; c0 += st->chunk, ++pass) {
     const int cnt = std::min(st->chunk, st->nc - c0);
@@ -711,11 +717,11 @@ static tk_status state_step_once(tk_state* st) {
     prof_begin(ctx, KID_EXPAND, &ev, sq);
     e = launch_expand(d, c0, cnt, X, st->mixed, st->oblique ? 1 : 0, obl, obn, sq);
     prof_end(ctx, KID_EXPAND, ev, sq);
-    if (e != hipSuccess) return ctx_hip(ctx, e, "expand");
+    if (e != hipSuccess) return fail("expand");
     prof_begin(ctx, KID_GRAM, &ev, sq);
     e = launch_gram(st->N, cnt, X, st->mixed, G, sq);
     prof_end(ctx, KID_GRAM, ev, sq);
-    if (e != hipSuccess) return ctx_hip(ctx, e, "gram");
+    if (e != hipSuccess) return fail("gram");
     prof_begin(ctx, KID_EIG, &ev, sq);
     if (st->mixed) {
       e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
@@ -730,11 +736,11 @@ static tk_status state_step_once(tk_state* st) {
                        nullptr, 1e-15, 1e-18, sq);
     }
     prof_end(ctx, KID_EIG, ev, sq);
-    if (e != hipSuccess) return ctx_hip(ctx, e, "eig");
+    if (e != hipSuccess) return fail("eig");
     prof_begin(ctx, KID_PROJECT, &ev, sq);
     e = launch_project(st->N, cnt, X, st->mixed, c0, st->CS, d.fac_n, d.rank_n, d.core_n, sq);
     prof_end(ctx, KID_PROJECT, ev, sq);
-    if (e != hipSuccess) return ctx_hip(ctx, e, "project");
+    if (e != hipSuccess) return fail("project");
   }
   if (dual) {
     e = hipEventRecord(st->ev_join, st->q2);
