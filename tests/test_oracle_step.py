@@ -215,3 +215,60 @@ def test_time_step_reading():
     S = fv.Setup(mesh, cfg, m0)
     nu0 = (m0[:, 0] * m0[:, 4] ** 0.5 / 0.1).max()
     assert abs(S.dt - 0.5 / (3 * 4.5 * 8 + nu0)) < 1e-15
+
+
+def _mixture_box():
+    """A spatially uniform periodic box whose f is a two-Maxwellian mixture.
+
+    Transport cancels exactly on a uniform periodic state, so one step is
+    f' = f + dt J(f) in every cell.  With J = nu (f_S - f) (eq.
+    shakhov_integral) and the heat flux of f_S equal to (1 - Pr) q, the
+    step keeps n, u, T and scales the heat flux by 1 - dt nu Pr.  The grid
+    (N = 48 on [-7, 7]) integrates these Gaussians to about 1e-15.
+    """
+    comps = [(0.7, (0.4, -0.2, 0.1), 0.9), (0.5, (-0.3, 0.25, 0.0), 1.3)]
+    cfg = small_cfg(N=48, xi_max=7.0, Kn=0.05, tol=0.0, cap=8)
+    mesh = synth.periodic_box(3, length=6.0)
+    xi, dxi = kin.grid(48, 7.0)
+    full = sum(kin.maxwell_full(n, np.array(u), T, xi) for n, u, T in comps)
+    parts = [kin.maxwell_rank1(n, np.array(u), T, xi) for n, u, T in comps]
+    tuck = tk.add(parts[0], parts[1])
+    n, u, T, q = kin.macros_full(full, xi, dxi)
+    m0 = np.tile(np.array([n, *u, T]), (mesh["n_cells"], 1))
+    S = fv.Setup(mesh, cfg, m0)
+    # nu = p / mu with p = m n R_g T and mu = (Kn / 2) T^omega (a reading:
+    # the paper is dimensional; parity unpinned beyond its role as the rate)
+    nu = n * 0.5 * T / (0.5 * cfg["Kn"] * T ** cfg["omega"])
+    return S, full, tuck, (n, u, T, q), nu
+
+
+def _check_collision_step(S, macros_after, before, nu):
+    n, u, T, q = before
+    n1, u1, T1, q1 = macros_after
+    c = np.sqrt(T)
+    assert abs(n1 - n) / n < 1e-13
+    assert np.abs(u1 - u).max() / c < 1e-13
+    assert abs(T1 - T) / T < 1e-13
+    expect = (1.0 - S.dt * nu * S.Pr) * q
+    assert 0.2 < S.dt * nu < 0.6  # the collision term moves q well beyond the tolerance
+    np.testing.assert_allclose(q1, expect, rtol=1e-12, atol=1e-12 * np.abs(q).max())
+
+
+def test_collision_step_direction_and_rate_full():
+    """O1: f' = f + dt nu (f_S - f) on a uniform mixture: n, u, T kept, q' = (1 - dt nu Pr) q."""
+    S, full, _, before, nu = _mixture_box()
+    F = {i: full for i in range(S.mesh["n_cells"])}
+    for i in (0, 5):
+        X = dvm.update_full(S, i, lambda c: F[c])
+        _check_collision_step(S, kin.macros_full(X, S.xi, S.dxi), before, nu)
+    out = dvm.step_full(S, F, cells=[3])
+    _check_collision_step(S, kin.macros_tucker(out[3], S.xi, S.dxi), before, nu)
+
+
+def test_collision_step_direction_and_rate_tucker():
+    """O2: the same step in Tucker form (exact rounding, tol 0)."""
+    S, _, tuck, before, nu = _mixture_box()
+    st = {i: tuck for i in range(S.mesh["n_cells"])}
+    out = td.step(S, st, cells=[0, 13])
+    for i in (0, 13):
+        _check_collision_step(S, kin.macros_tucker(out[i], S.xi, S.dxi), before, nu)
