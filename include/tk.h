@@ -240,6 +240,29 @@ tk_status tk_state_export(tk_state* st, int32_t cell, tk_tucker* out);
 tk_status tk_round_tucker(tk_ctx* ctx, int32_t count, const tk_tucker* in, double tol,
                           int32_t cap, tk_tucker* out);
 
+/* Op4 on device-resident Tucker tensors with no device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  The same rounding as
+ * tk_round_tucker (same kernels, same results).  Buffers are caller-owned
+ * device memory in the state layout:
+ *   core_in[count][in_cap^3]    (k1 + in_cap (k2 + in_cap k3)),
+ *   fac_in[count][3][in_cap][N] (column k of mode a: N contiguous values),
+ *   rank_in[count][3]           (each in 1..in_cap; a value outside is
+ *                                clamped into that range by the kernels),
+ * and the outputs core_out[count][cap^3], fac_out[count][3][cap][N],
+ * rank_out[count][3] in the same layout with cap in place of in_cap
+ * (entries beyond the ranks are written as zeros).  N is 16, 24 or 32,
+ * in_cap and cap in 1..16 and <= N, otherwise TK_EINVAL.  Work space comes
+ * from a fixed 32 MiB device array of the library (one copy per GPU, kept
+ * until the process ends): tensors are processed in passes of as many as
+ * fit it (107 at N = 32).  Enqueued on the context stream without waiting;
+ * the caller synchronises (tk_sync) before reading the outputs.  Calls
+ * share that array: calls that overlap on one GPU (from different contexts
+ * or streams) race.  Calls no allocating routine of HIP or any library.   */
+tk_status tk_round_tucker_noalloc(tk_ctx* ctx, int32_t N, int32_t count, int32_t in_cap, const double* core_in,
+                                  const double* fac_in, const int32_t* rank_in, double tol, int32_t cap,
+                                  double* core_out, double* fac_out, int32_t* rank_out);
+
 /* ---- plain full-tensor comparator -------------------------------------- */
 /* The same step with N^3 values stored per cell and no rounding (the
  * paper's baseline discrete velocity method).  Precision TK_FP64 stores

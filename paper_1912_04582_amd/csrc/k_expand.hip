@@ -1224,7 +1224,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand_plain(int CS, const double* co
   int pf[FIB];
 #pragma unroll
   for (int f = 0; f < FIB; ++f) pf[f] = threadIdx.x + BLOCK * f;
-  const int r1 = rank[3 * c], r2 = rank[3 * c + 1], r3 = rank[3 * c + 2];
+  // ranks clamped to 1..CS, so that device-resident ranks outside that range
+  // (never produced by this library) keep every access inside the layout
+  auto clampr = [CS](int r) { return r < 1 ? 1 : (r > CS ? CS : r); };
+  const int r1 = clampr(rank[3 * c]), r2 = clampr(rank[3 * c + 1]), r3 = clampr(rank[3 * c + 2]);
   stage_state<N, BLOCK, double>(core, fac, CS, c, r1, r2, r3, -1, -1, nullptr, 1.0, sU, sG);
   __syncthreads();
   double acc[FIB][N];

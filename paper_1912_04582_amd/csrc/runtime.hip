@@ -26,6 +26,38 @@ const char* kKernelNames[KID_COUNT] = {"moments", "expand", "gram", "eig", "proj
 using namespace tk;
 
 // ---------------------------------------------------------------------------
+// Scratch of tk_round_tucker_noalloc: device memory that the library never
+// allocates at run time.  Every GPU that loads the library holds its own
+// copy of this array until the process ends.  In host code the name is only
+// a host-side stand-in: kernels and copies take the device address that
+// hipGetSymbolAddress returns for the current device (scratch_lookup).
+
+constexpr size_t kScratchBytes = size_t(32) << 20;  // 32 MiB per device
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device.
+static hipError_t scratch_lookup(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
 // context helpers
 
 tk_status ctx_fail(tk_ctx* ctx, tk_status st, const std::string& msg) {
@@ -907,6 +939,7 @@ tk_status tk_ctx_create(int32_t device, size_t hbm_budget, void* hip_stream, tk_
   size_t freeb = 0, total = 0;
   if (hipMemGetInfo(&freeb, &total) != hipSuccess) return TK_EDEVICE;
   c->budget = hbm_budget ? hbm_budget : (size_t)(0.9 * (double)freeb);
+  if (scratch_lookup(device, &c->scratch) != hipSuccess) return TK_EDEVICE;
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
     c->own_stream = false;
@@ -1391,6 +1424,49 @@ tk_status tk_round_tucker(tk_ctx* ctx, int32_t count, const tk_tucker* in, doubl
         for (int i = 0; i < N; ++i) t.U[a][i + N * c] = fo[(((size_t)k * 3 + a) * CSo + c) * N + i];
   }
   return TK_OK;
+}
+
+tk_status tk_round_tucker_noalloc(tk_ctx* ctx, int32_t N, int32_t count, int32_t in_cap, const double* core_in,
+                                  const double* fac_in, const int32_t* rank_in, double tol, int32_t cap,
+                                  double* core_out, double* fac_out, int32_t* rank_out) {
+  if (!ctx || count < 0) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  if (ctx->device < 0) return ctx_fail(ctx, TK_EDEVICE, "round (no allocation): host-only context");
+  if (!ctx->scratch) return ctx_fail(ctx, TK_EDEVICE, "round (no allocation): scratch array not set up");
+  if (N != 16 && N != 24 && N != 32) return ctx_fail(ctx, TK_EINVAL, "round (no allocation): N must be 16, 24 or 32");
+  if (in_cap < 1 || in_cap > kMaxCap || in_cap > N)
+    return ctx_fail(ctx, TK_EINVAL, "round (no allocation): in_cap must be in 1..16 and <= N");
+  if (cap < 1 || cap > kMaxCap || cap > N || !(tol >= 0))
+    return ctx_fail(ctx, TK_EINVAL, "round (no allocation): bad tol or cap");
+  if (count == 0) return TK_OK;
+  if (!core_in || !fac_in || !rank_in || !core_out || !fac_out || !rank_out)
+    return ctx_fail(ctx, TK_EINVAL, "round (no allocation): null buffer");
+  // per tensor: the expanded N^3 tensor, three Grams and three first-pass bases
+  const size_t nn = (size_t)N * N;
+  const size_t per = sizeof(double) * (nn * N + 6 * nn);
+  const int pass = (int)std::min<size_t>((size_t)count, kScratchBytes / per);
+  if (pass < 1) return ctx_fail(ctx, TK_EINVAL, "round (no allocation): one tensor exceeds the scratch array");
+  double* X = static_cast<double*>(ctx->scratch);
+  double* G = X + (size_t)pass * nn * N;
+  double* W = G + (size_t)pass * 3 * nn;
+  const size_t ci = (size_t)in_cap * in_cap * in_cap, co = (size_t)cap * cap * cap;
+  hipStream_t q = ctx->stream;
+  hipError_t e = hipSuccess;
+  for (int p0 = 0; p0 < count && e == hipSuccess; p0 += pass) {
+    const int n = std::min(pass, count - p0);
+    double* fo = fac_out + (size_t)p0 * 3 * cap * N;
+    int* ro = rank_out + 3 * (size_t)p0;
+    e = launch_expand_plain(N, n, in_cap, core_in + (size_t)p0 * ci, fac_in + (size_t)p0 * 3 * in_cap * N,
+                            rank_in + 3 * (size_t)p0, X, q);
+    if (e == hipSuccess) e = launch_gram(N, n, X, 0, G, q);
+    if (e == hipSuccess)
+      e = launch_eig(N, n, G, nullptr, nullptr, 0, tol, cap, cap, fo, ro, nullptr, W, nullptr, 1e-15, 1e-18, q);
+    if (e == hipSuccess) e = launch_gram_rot(N, n, X, 0, W, G, q);
+    if (e == hipSuccess)
+      e = launch_eig(N, n, G, nullptr, nullptr, 0, tol, cap, cap, fo, ro, W, nullptr, nullptr, 1e-15, 1e-18, q);
+    if (e == hipSuccess) e = launch_project(N, n, X, 0, 0, cap, fo, ro, core_out + (size_t)p0 * co, q);
+  }
+  return ctx_hip(ctx, e, "round (no allocation)");
 }
 
 }  // extern "C"

@@ -13,6 +13,9 @@ struct tk_ctx {
   size_t budget = 0;
   size_t used = 0;
   std::map<void*, size_t> sizes;
+  // device address of this device's copy of the no-allocation rounding
+  // scratch array (runtime.hip), looked up once per device at context set-up
+  void* scratch = nullptr;
   std::string err;
   std::recursive_mutex mu;
   // per-kernel-family timing

@@ -27,7 +27,8 @@ EXPORTED = [
     "tk_prof_reset", "tk_prof_eig", "tk_mesh_load", "tk_mesh_destroy", "tk_state_init", "tk_state_init_batch",
     "tk_state_destroy", "tk_state_info", "tk_state_dt", "tk_state_set_chunk", "tk_state_chunk",
     "tk_state_tune", "tk_state_use_graph", "tk_state_streams", "tk_state_checkpoint", "tk_state_restore", "tk_moments", "tk_step", "tk_step_async",
-    "tk_state_ranks", "tk_state_export", "tk_round_tucker", "tk_plain_init", "tk_serve_create",
+    "tk_state_ranks", "tk_state_export", "tk_round_tucker", "tk_round_tucker_noalloc", "tk_plain_init",
+    "tk_serve_create",
     "tk_serve_submit", "tk_serve_poll", "tk_serve_destroy",
 ]
 
@@ -115,6 +116,8 @@ def lib():
             "tk_state_export": [P, C.c_int32, C.POINTER(tk_tucker)],
             "tk_round_tucker": [P, C.c_int32, C.POINTER(tk_tucker), C.c_double, C.c_int32,
                                 C.POINTER(tk_tucker)],
+            "tk_round_tucker_noalloc": [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_int32,
+                                        P, P, P],
             "tk_serve_create": [P, C.c_size_t, C.POINTER(P)],
             "tk_serve_submit": [P, C.POINTER(tk_request), C.POINTER(C.c_uint64)],
             "tk_serve_poll": [P, C.c_uint64, C.POINTER(tk_result)],
@@ -236,6 +239,16 @@ class Context:
             U = [ou[a][:N * r[a]].reshape((N, r[a]), order="F").copy() for a in range(3)]
             res.append((G, U))
         return res
+
+    def round_tucker_noalloc(self, N, count, in_cap, core_in, fac_in, rank_in, tol, cap, core_out, fac_out,
+                             rank_out):
+        """tk_round_tucker_noalloc on caller-owned device buffers given as raw
+        device addresses (ints), enqueued on the context stream; call sync()
+        before reading the outputs."""
+        _check(lib().tk_round_tucker_noalloc(self.h, int(N), int(count), int(in_cap), C.c_void_p(core_in),
+                                             C.c_void_p(fac_in), C.c_void_p(rank_in), float(tol), int(cap),
+                                             C.c_void_p(core_out), C.c_void_p(fac_out), C.c_void_p(rank_out)),
+               self.h)
 
 
 class Mesh:
