@@ -220,22 +220,27 @@ def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True, one_stream=Fal
         ctx.prof_reset()
         ctx.prof_enable(prof)
         ctx.eig_stats(reset=True)
+        if not plain:
+            st.rounding()
         r0 = None if plain else st.ranks()[0]
         t0 = time.perf_counter()
         st.step(steps)  # waits for completion
         t1 = time.perf_counter()
         ctx.prof_enable(False)
-        fams = ["moments", "expand", "gram", "eig", "project"] if not plain else ["plain_moments", "plain_step"]
+        fams = ["moments", "rround", "expand", "gram", "eig", "project"] if not plain else ["plain_moments", "plain_step"]
         prof_ms = {f: ctx.prof_get(f) for f in fams}
         eig = ctx.eig_stats(reset=True)
+        rcount = None
         if not plain:
+            rcount = st.rounding()
             log(f"  eigensolver: {eig}")
+            log(f"  rounding paths (cell-updates): {rcount}")
         r1, C = (None, None) if plain else st.ranks()
         st.close()
         tm.close()
     finally:
         ctx.close()
-    return dict(seconds=t1 - t0, prof=prof_ms, ranks0=r0, ranks1=r1, compression=C)
+    return dict(seconds=t1 - t0, prof=prof_ms, ranks0=r0, ranks1=r1, compression=C, rounding_paths=rcount)
 
 
 def run_batch(steps, warmup, count, prof_steps=3):

@@ -63,7 +63,8 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
                                                      int c0, double tol_o, int cap_o, int CS, double* fac_n,
                                                      int* rank_n, const double* Win, double* Wout, double* Wkeep,
                                                      double rel_thr, double abs_fac, double drop,
-                                                     const int* rank_prev, int lead) {
+                                                     const int* rank_prev, int lead, const int* cells,
+                                                     const int* cells_n, int* wvalid) {
   constexpr int NT = kEigThreads;
   constexpr int LD = N + 1;
   constexpr int NH = N / 2;
@@ -78,10 +79,16 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
   __shared__ int s_rank, s_fast;
   const int m = blockIdx.x;
   const int cl = m / 3, mode = m % 3;
-  const int cell = c0 + cl;
+  // a pass over a device-side cell list ends at its count
+  if (cells && c0 + cl >= *cells_n) return;
+  const int cell = cells ? cells[c0 + cl] : c0 + cl;
   const int lane = threadIdx.x;
   const double* g = Gm + (size_t)m * N * N;
   double* wk = Wkeep ? Wkeep + ((size_t)cell * 3 + mode) * N * N : nullptr;
+  // the kept basis is a usable warm start unless the cell was last rounded
+  // in the space of its concatenated factors (it is written again below)
+  // (one flag per cell and mode, read and written only by this workgroup)
+  const double* wr = (wk && (!wvalid || wvalid[3 * cell + mode])) ? wk : nullptr;
   double tol = tol_o;
   int cap = cap_o;
   if (inst) {
@@ -91,7 +98,7 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
   }
   // the matrix, the previous basis (V[i][j]: entry i of vector j) and the
   // previous rank, all requested before any is used
-  const int rp = (wk && lead > 0 && rank_prev) ? rank_prev[3 * cell + mode] : 0;
+  const int rp = (wr && lead > 0 && rank_prev) ? rank_prev[3 * cell + mode] : 0;
   {
     constexpr int PER = (N * N + NT - 1) / NT;
     double ga[PER], wa[PER];
@@ -100,7 +107,7 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
       const int o = lane + t * NT;
       if (o < N * N) {
         ga[t] = g[o];
-        wa[t] = wk ? wk[o] : (((o / N) == (o % N)) ? 1.0 : 0.0);
+        wa[t] = wr ? wr[o] : (((o / N) == (o % N)) ? 1.0 : 0.0);
       }
     }
 #pragma unroll
@@ -114,7 +121,7 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
   }
   // leading block size (N: the full matrix)
   int k = N;
-  if (wk && lead > 0 && rank_prev) {
+  if (wr && lead > 0 && rank_prev) {
     k = (rp < 1 ? 1 : rp) + lead;
     k += k & 1;
     if (k > N) k = N;
@@ -219,7 +226,7 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
     k += 12;
     if (k > N) k = N;
   }
-  if (wk) {
+  if (wr) {
     // ---- full warm start: A <- V^T G V through Tm = G V --------------------
     for (int o = lane; o < N * N; o += NT) {
       const int i = o / N, j = o % N;
@@ -246,6 +253,7 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
       const int kk = o / N, i = o % N;
       wk[o] = V[i * LD + order[kk]];
     }
+    if (wvalid && lane == 0) wvalid[3 * cell + mode] = 1;
   }
   if (Wout) {
     // full sorted basis (premultiplied by Win when given), no truncation
@@ -330,11 +338,13 @@ __global__ void k_identity_basis(int N, size_t count, double* W) {
 hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
                       double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
                       const double* Win, double* Wout, double* Wkeep, double rel_thr, double abs_fac,
-                      hipStream_t s, double drop, const int* rank_prev, int lead) {
+                      hipStream_t s, double drop, const int* rank_prev, int lead, const int* cells,
+                      const int* cells_n, int* wvalid) {
   if (count <= 0) return hipSuccess;
   dim3 grid(3 * count), blk(kEigThreads);
 #define TK_EIG(NN) hipLaunchKernelGGL(k_eig<NN>, grid, blk, 0, s, G, inst, ip, c0, tol_override, cap_override, CS, \
-                                      fac_n, rank_n, Win, Wout, Wkeep, rel_thr, abs_fac, drop, rank_prev, lead)
+                                      fac_n, rank_n, Win, Wout, Wkeep, rel_thr, abs_fac, drop, rank_prev, lead, \
+                                      cells, cells_n, wvalid)
   switch (N) {
     case 16: TK_EIG(16); break;
     case 24: TK_EIG(24); break;

@@ -132,7 +132,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
   T* sFU = sY + CS * CS * N;      // 3 CS N   f_S factors
   T* sFG = sFU + 3 * CS * N;      // 64       f_S core
   const int cb = blockIdx.x / SPLIT, part = blockIdx.x % SPLIT;
-  const int c = c0 + cb;
+  if (d.cells && c0 + cb >= *d.cells_n) return;
+  const int c = d.cells ? d.cells[c0 + cb] : c0 + cb;
   const int tid = threadIdx.x;
   const InstParams P = d.ip[d.inst[c]];
   const double nu = d.nu[c];
@@ -425,8 +426,10 @@ __global__ __launch_bounds__(BLOCK, RB > 0 ? 6 : 1) void k_expand_pipe(DevState 
   if constexpr (LIST == 2) {
     if (cb >= *list_n) return;
     cb = list[cb];
+  } else {
+    if (d.cells && c0 + cb >= *d.cells_n) return;
   }
-  const int c = c0 + cb;
+  const int c = d.cells ? d.cells[c0 + cb] : c0 + cb;
   const int tid = threadIdx.x;
   const InstParams P = d.ip[d.inst[c]];
   const double nu = d.nu[c];

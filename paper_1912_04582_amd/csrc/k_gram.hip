@@ -27,12 +27,13 @@ __device__ inline void ld4(const double* p, double (&o)[4]) {
 }
 
 template <int N, typename T>
-__global__ __launch_bounds__(192) void k_gram(const T* X, double* G) {
+__global__ __launch_bounds__(192) void k_gram(const T* X, double* G, int c0, const int* cells_n) {
   constexpr int NB = (N + 15) / 16;  // 16-row blocks
   constexpr int NP = NB * (NB + 1) / 2;
   // one workgroup per cell, one wavefront per mode: the three waves read the
   // same tensor at the same time, on the same CU
   const int cell = blockIdx.x;
+  if (cells_n && c0 + cell >= *cells_n) return;
   const int mode = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int ii = lane & 15;  // row within block (A) / column within block (B)
@@ -215,7 +216,8 @@ constexpr size_t gram_lds_bytes() {
 // vector arithmetic over chunks of CH unfolding columns.  W holds the
 // first-pass basis as rows: W[k][i] is entry i of basis vector k.
 template <int N, typename T>
-__global__ __launch_bounds__(256) void k_gram_rot(const T* X, const double* Wb, double* G2) {
+__global__ __launch_bounds__(256) void k_gram_rot(const T* X, const double* Wb, double* G2, int c0,
+                                                   const int* cells_n) {
   constexpr int CH = 64;
   constexpr int PER = (N * N + 255) / 256;
   __shared__ double W[N * N];
@@ -223,6 +225,7 @@ __global__ __launch_bounds__(256) void k_gram_rot(const T* X, const double* Wb, 
   __shared__ double Bc[N * (CH + 1)];
   const int m = blockIdx.x;
   const int cell = m / 3, mode = m % 3;
+  if (cells_n && c0 + cell >= *cells_n) return;
   const int tid = threadIdx.x;
   const T* x = X + (size_t)cell * N * N * N;
   for (int o = tid; o < N * N; o += 256) W[o] = Wb[(size_t)m * N * N + o];
@@ -269,23 +272,23 @@ __global__ __launch_bounds__(256) void k_gram_rot(const T* X, const double* Wb, 
 }  // namespace
 
 hipError_t launch_gram_rot(int N, int count, const void* X, int mixed, const double* W, double* G2,
-                           hipStream_t s) {
+                           hipStream_t s, int c0, const int* cells_n) {
   if (count <= 0) return hipSuccess;
   dim3 grid(3 * count), blk(256);
   if (mixed) {
     const float* x = (const float*)X;
     switch (N) {
-      case 16: hipLaunchKernelGGL((k_gram_rot<16, float>), grid, blk, 0, s, x, W, G2); break;
-      case 24: hipLaunchKernelGGL((k_gram_rot<24, float>), grid, blk, 0, s, x, W, G2); break;
-      case 32: hipLaunchKernelGGL((k_gram_rot<32, float>), grid, blk, 0, s, x, W, G2); break;
+      case 16: hipLaunchKernelGGL((k_gram_rot<16, float>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
+      case 24: hipLaunchKernelGGL((k_gram_rot<24, float>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
+      case 32: hipLaunchKernelGGL((k_gram_rot<32, float>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     const double* x = (const double*)X;
     switch (N) {
-      case 16: hipLaunchKernelGGL((k_gram_rot<16, double>), grid, blk, 0, s, x, W, G2); break;
-      case 24: hipLaunchKernelGGL((k_gram_rot<24, double>), grid, blk, 0, s, x, W, G2); break;
-      case 32: hipLaunchKernelGGL((k_gram_rot<32, double>), grid, blk, 0, s, x, W, G2); break;
+      case 16: hipLaunchKernelGGL((k_gram_rot<16, double>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
+      case 24: hipLaunchKernelGGL((k_gram_rot<24, double>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
+      case 32: hipLaunchKernelGGL((k_gram_rot<32, double>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -303,25 +306,26 @@ hipError_t launch_gram_lds_t(int count, const void* X, double* G, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hipStream_t s) {
+hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hipStream_t s, int c0,
+                       const int* cells_n) {
   if (count <= 0) return hipSuccess;
   dim3 grid(count), blk(192);
   if (mixed) {
     const float* x = (const float*)X;
     switch (N) {
-      case 16: hipLaunchKernelGGL((k_gram<16, float>), grid, blk, 0, s, x, G); break;
-      case 24: hipLaunchKernelGGL((k_gram<24, float>), grid, blk, 0, s, x, G); break;
-      case 32: hipLaunchKernelGGL((k_gram<32, float>), grid, blk, 0, s, x, G); break;
-      case 48: hipLaunchKernelGGL((k_gram<48, float>), grid, blk, 0, s, x, G); break;
+      case 16: hipLaunchKernelGGL((k_gram<16, float>), grid, blk, 0, s, x, G, c0, cells_n); break;
+      case 24: hipLaunchKernelGGL((k_gram<24, float>), grid, blk, 0, s, x, G, c0, cells_n); break;
+      case 32: hipLaunchKernelGGL((k_gram<32, float>), grid, blk, 0, s, x, G, c0, cells_n); break;
+      case 48: hipLaunchKernelGGL((k_gram<48, float>), grid, blk, 0, s, x, G, c0, cells_n); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     const double* x = (const double*)X;
     switch (N) {
-      case 16: hipLaunchKernelGGL((k_gram<16, double>), grid, blk, 0, s, x, G); break;
-      case 24: hipLaunchKernelGGL((k_gram<24, double>), grid, blk, 0, s, x, G); break;
-      case 32: hipLaunchKernelGGL((k_gram<32, double>), grid, blk, 0, s, x, G); break;
-      case 48: hipLaunchKernelGGL((k_gram<48, double>), grid, blk, 0, s, x, G); break;
+      case 16: hipLaunchKernelGGL((k_gram<16, double>), grid, blk, 0, s, x, G, c0, cells_n); break;
+      case 24: hipLaunchKernelGGL((k_gram<24, double>), grid, blk, 0, s, x, G, c0, cells_n); break;
+      case 32: hipLaunchKernelGGL((k_gram<32, double>), grid, blk, 0, s, x, G, c0, cells_n); break;
+      case 48: hipLaunchKernelGGL((k_gram<48, double>), grid, blk, 0, s, x, G, c0, cells_n); break;
       default: return hipErrorInvalidValue;
     }
   }

@@ -13,14 +13,16 @@ constexpr int kProjThreads = 256;
 
 template <int N, typename T>
 __global__ __launch_bounds__(kProjThreads) void k_project(const T* X, int c0, int CS, const double* fac_n,
-                                                         const int* rank_n, double* core_n) {
+                                                         const int* rank_n, double* core_n, const int* cells,
+                                                         const int* cells_n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sS = reinterpret_cast<double*>(smem_raw);  // N*N slice
   double* sW = sS + N * N;                             // 3 * CS * N
   double* sQ = sW + 3 * CS * N;                        // CS * N
   double* sT = sQ + CS * N;                            // CS * CS
   const int cl = blockIdx.x;
-  const int cell = c0 + cl;
+  if (cells && c0 + cl >= *cells_n) return;
+  const int cell = cells ? cells[c0 + cl] : c0 + cl;
   const int tid = threadIdx.x;
   const int r1 = rank_n[3 * cell], r2 = rank_n[3 * cell + 1], r3 = rank_n[3 * cell + 2];
   for (int o = tid; o < 3 * CS * N; o += kProjThreads)
@@ -89,13 +91,15 @@ __global__ __launch_bounds__(kProjThreads) void k_project(const T* X, int c0, in
 template <int N, typename T>
 __global__ __launch_bounds__(kProjThreads) void k_project_fib(const T* X, int c0, int CS, const double* fac_n,
                                                              const int* rank_n, double* core_n, int cap,
-                                                             int lo, int hi) {
+                                                             int lo, int hi, const int* cells,
+                                                             const int* cells_n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sW = reinterpret_cast<double*>(smem_raw);    // 3 CS N
   double* sY2 = sW + 3 * CS * N;                       // cap cap N
   T* sY1 = reinterpret_cast<T*>(sY2 + cap * cap * N);  // cap N^2
   const int cl = blockIdx.x;
-  const int cell = c0 + cl;
+  if (cells && c0 + cl >= *cells_n) return;
+  const int cell = cells ? cells[c0 + cl] : c0 + cl;
   const int tid = threadIdx.x;
   const int r1 = rank_n[3 * cell], r2 = rank_n[3 * cell + 1], r3 = rank_n[3 * cell + 2];
   const int r12 = r1 > r2 ? r1 : r2;
@@ -148,7 +152,7 @@ constexpr int kProjTier[2] = {6, 9};
 
 template <int N, typename T>
 hipError_t launch_project_t(int count, const void* X, int c0, int CS, const double* fac_n, const int* rank_n,
-                            double* core_n, hipStream_t s) {
+                            double* core_n, hipStream_t s, const int* cells, const int* cells_n) {
   const size_t shf = project_fib_bytes<N, T>(CS, CS);
   if (shf <= 96 * 1024) {
     auto k = k_project_fib<N, T>;
@@ -159,35 +163,36 @@ hipError_t launch_project_t(int count, const void* X, int c0, int CS, const doub
       const int hi = (t < 2 && kProjTier[t] < CS) ? kProjTier[t] : CS;
       const size_t sh = project_fib_bytes<N, T>(CS, hi);
       hipLaunchKernelGGL(k, dim3(count), dim3(kProjThreads), sh, s, (const T*)X, c0, CS, fac_n, rank_n, core_n, hi,
-                         lo, hi);
+                         lo, hi, cells, cells_n);
       lo = hi;
     }
     return hipGetLastError();
   }
   const size_t sh = sizeof(double) * (N * N + 3 * CS * N + CS * N + CS * CS);
   hipLaunchKernelGGL((k_project<N, T>), dim3(count), dim3(kProjThreads), sh, s, (const T*)X, c0, CS, fac_n,
-                     rank_n, core_n);
+                     rank_n, core_n, cells, cells_n);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_project(int N, int count, const void* X, int mixed, int c0, int CS, const double* fac_n,
-                          const int* rank_n, double* core_n, hipStream_t s) {
+                          const int* rank_n, double* core_n, hipStream_t s, const int* cells,
+                          const int* cells_n) {
   if (count <= 0) return hipSuccess;
   if (mixed) {
     switch (N) {
-      case 16: return launch_project_t<16, float>(count, X, c0, CS, fac_n, rank_n, core_n, s);
-      case 24: return launch_project_t<24, float>(count, X, c0, CS, fac_n, rank_n, core_n, s);
-      case 32: return launch_project_t<32, float>(count, X, c0, CS, fac_n, rank_n, core_n, s);
-      case 48: return launch_project_t<48, float>(count, X, c0, CS, fac_n, rank_n, core_n, s);
+      case 16: return launch_project_t<16, float>(count, X, c0, CS, fac_n, rank_n, core_n, s, cells, cells_n);
+      case 24: return launch_project_t<24, float>(count, X, c0, CS, fac_n, rank_n, core_n, s, cells, cells_n);
+      case 32: return launch_project_t<32, float>(count, X, c0, CS, fac_n, rank_n, core_n, s, cells, cells_n);
+      case 48: return launch_project_t<48, float>(count, X, c0, CS, fac_n, rank_n, core_n, s, cells, cells_n);
     }
   } else {
     switch (N) {
-      case 16: return launch_project_t<16, double>(count, X, c0, CS, fac_n, rank_n, core_n, s);
-      case 24: return launch_project_t<24, double>(count, X, c0, CS, fac_n, rank_n, core_n, s);
-      case 32: return launch_project_t<32, double>(count, X, c0, CS, fac_n, rank_n, core_n, s);
-      case 48: return launch_project_t<48, double>(count, X, c0, CS, fac_n, rank_n, core_n, s);
+      case 16: return launch_project_t<16, double>(count, X, c0, CS, fac_n, rank_n, core_n, s, cells, cells_n);
+      case 24: return launch_project_t<24, double>(count, X, c0, CS, fac_n, rank_n, core_n, s, cells, cells_n);
+      case 32: return launch_project_t<32, double>(count, X, c0, CS, fac_n, rank_n, core_n, s, cells, cells_n);
+      case 48: return launch_project_t<48, double>(count, X, c0, CS, fac_n, rank_n, core_n, s, cells, cells_n);
     }
   }
   return hipErrorInvalidValue;

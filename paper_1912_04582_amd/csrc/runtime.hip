@@ -20,7 +20,7 @@
 
 namespace tk {
 const char* kKernelNames[KID_COUNT] = {"moments", "expand", "gram", "eig", "project", "init",
-                                       "plain_moments", "plain_step", "residual"};
+                                       "plain_moments", "plain_step", "residual", "rround"};
 }
 
 using namespace tk;
@@ -270,6 +270,8 @@ void state_free(tk_state* st) {
   st->q2 = nullptr;
   for (void* p : st->allocs) ctx_free(ctx, p);
   st->allocs.clear();
+  if (st->h_rcnt) (void)hipHostFree(st->h_rcnt);
+  st->h_rcnt = nullptr;
 }
 
 static void* st_alloc(tk_state* st, size_t bytes, tk_status* s) {
@@ -306,6 +308,8 @@ DevState state_dev(const tk_state* st) {
   d.est_core = st->d_est_core;
   d.est_fac = st->d_est_fac;
   d.est_rank = st->d_est_rank;
+  d.cells = nullptr;
+  d.cells_n = nullptr;
   return d;
 }
 
@@ -342,6 +346,7 @@ size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk) {
     const size_t ch = std::min<size_t>((size_t)nc, (size_t)chunk);
     b += 2 * (size_t)nc * (CS * CS * CS + 3 * CS * N) * 8 + 2 * (size_t)nc * 3 * 4;
     b += (size_t)nc * 3 * N * N * 8;                      // warm-start eigenbases
+    b += (size_t)nc * (4 + 4 + 12);                       // rounding lists, basis validity
     b += ch * (N * N * N * tsz + 3 * N * N * 8);          // X and Gram workspaces
     if (p.precision == TK_FP64) b += ch * 3 * N * N * 8;  // first-pass bases
     b += (size_t)nc * kSlots * (3 * 8 + 4);               // oblique slots
@@ -535,6 +540,20 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     ALLOC(ob_n, int, 1);
     if (!S->mixed) ALLOC(Wb, double, (size_t)S->chunk * 3 * N * N);
     ALLOC(Wkeep, double, (size_t)nc * 3 * N * N);
+    ALLOC(d_wvalid, int, (size_t)nc * 3);
+    ALLOC(d_rstats, unsigned long long, 8);
+    S->rspace = !oblique && N <= 32;
+    if (S->rspace) {
+      ALLOC(d_rlistM, int, nc);
+      ALLOC(d_rlistD, int, nc);
+      ALLOC(d_rcnt, int, 2);
+      if (hipHostMalloc((void**)&S->h_rcnt, sizeof(int), 0) != hipSuccess) {
+        S->h_rcnt = nullptr;
+        state_free(S);
+        return ctx_fail(ctx, TK_EDEVICE, "state: pinned host word");
+      }
+      *S->h_rcnt = 0;
+    }
     // optional second workspace: only if it fits what the budget leaves
     // (with a margin), so that no error is recorded when it does not
     const size_t ch = (size_t)S->chunk;
@@ -594,6 +613,8 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     }
     if (e == hipSuccess) e = launch_init_maxwell(state_dev(S), S->d_macro5, q);
     if (e == hipSuccess) e = launch_identity_basis(N, (size_t)nc * 3, S->Wkeep, q);
+    if (e == hipSuccess) e = launch_fill_int(S->d_wvalid, (size_t)nc * 3, 1, q);
+    if (e == hipSuccess) e = hipMemsetAsync(S->d_rstats, 0, 8 * sizeof(unsigned long long), q);
     if (e == hipSuccess && oblique && n_est > 0) {
       // |xi . e| estimate of every oblique face: truncated HOSVD of the exact
       // tensor, mode ranks <= kEstCap, singular values <= kEstDrop sigma_1 dropped
@@ -720,6 +741,26 @@ static tk_status state_step_once(tk_state* st) {
   e = launch_moments(d, q);
   prof_end(ctx, KID_MOMENTS, ev);
   if (e != hipSuccess) return ctx_hip(ctx, e, "moments");
+  // rounding in the space of the concatenated factors: the cells it leaves
+  // (their concatenated ranks or core too large for its layouts) are listed
+  // for the N-basis passes below; an eager step reads their count back, a
+  // captured step runs passes over every cell that end at the list's count
+  int dense_n = st->nc;
+  if (st->rspace) {
+    prof_begin(ctx, KID_RROUND, &ev);
+    e = launch_rround(d, st->d_rlistM, st->d_rcnt, st->d_rlistD, st->d_rcnt + 1, st->d_wvalid, st->d_rstats, q);
+    prof_end(ctx, KID_RROUND, ev);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "rounding in factor space");
+    d.cells = st->d_rlistD;
+    d.cells_n = st->d_rcnt + 1;
+    if (!st->capturing) {
+      e = hipMemcpyAsync(st->h_rcnt, st->d_rcnt + 1, sizeof(int), hipMemcpyDeviceToHost, q);
+      if (e == hipSuccess) e = hipStreamSynchronize(q);
+      if (e != hipSuccess) return ctx_hip(ctx, e, "rounding list count");
+      dense_n = *st->h_rcnt;
+      st->dense_total += dense_n;
+    }
+  }
   // odd passes on the second stream with the second workspace: the passes
   // are independent (each reads the current state and writes its own cells
   // of the next one), and a stream reuses its workspace only after its
@@ -737,8 +778,8 @@ static tk_status state_step_once(tk_state* st) {
     return ctx_hip(ctx, e, what);
   };
   int pass = 0;
-  for (int c0 = 0; c0 < st->nc; c0 += st->chunk, ++pass) {
-    const int cnt = std::min(st->chunk, st->nc - c0);
+  for (int c0 = 0; c0 < dense_n; c0 += st->chunk, ++pass) {
+    const int cnt = std::min(st->chunk, dense_n - c0);
     const bool two = dual && (pass & 1);
     hipStream_t sq = two ? st->q2 : q;
     void* X = two ? st->X2 : st->X;
@@ -751,26 +792,27 @@ static tk_status state_step_once(tk_state* st) {
     prof_end(ctx, KID_EXPAND, ev, sq);
     if (e != hipSuccess) return fail("expand");
     prof_begin(ctx, KID_GRAM, &ev, sq);
-    e = launch_gram(st->N, cnt, X, st->mixed, G, sq);
+    e = launch_gram(st->N, cnt, X, st->mixed, G, sq, c0, d.cells_n);
     prof_end(ctx, KID_GRAM, ev, sq);
     if (e != hipSuccess) return fail("gram");
     prof_begin(ctx, KID_EIG, &ev, sq);
     if (st->mixed) {
       e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
-                     nullptr, st->Wkeep, 1e-12, 1e-15, sq, 0.0, st->warm ? d.rank : nullptr, st->warm ? 6 : 0);
+                     nullptr, st->Wkeep, 1e-12, 1e-15, sq, 0.0, st->warm ? d.rank : nullptr, st->warm ? 6 : 0,
+                     d.cells, d.cells_n, st->d_wvalid);
     } else {
       // FP64 path: first basis, Gram of the rotated unfoldings, final basis
       e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr, Wb,
-                     st->Wkeep, 1e-15, 1e-18, sq);
-      if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, X, 0, Wb, G, sq);
+                     st->Wkeep, 1e-15, 1e-18, sq, 0.0, nullptr, 0, d.cells, d.cells_n, st->d_wvalid);
+      if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, X, 0, Wb, G, sq, c0, d.cells_n);
       if (e == hipSuccess)
         e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, Wb, nullptr,
-                       nullptr, 1e-15, 1e-18, sq);
+                       nullptr, 1e-15, 1e-18, sq, 0.0, nullptr, 0, d.cells, d.cells_n, nullptr);
     }
     prof_end(ctx, KID_EIG, ev, sq);
     if (e != hipSuccess) return fail("eig");
     prof_begin(ctx, KID_PROJECT, &ev, sq);
-    e = launch_project(st->N, cnt, X, st->mixed, c0, st->CS, d.fac_n, d.rank_n, d.core_n, sq);
+    e = launch_project(st->N, cnt, X, st->mixed, c0, st->CS, d.fac_n, d.rank_n, d.core_n, sq, d.cells, d.cells_n);
     prof_end(ctx, KID_PROJECT, ev, sq);
     if (e != hipSuccess) return fail("project");
   }
@@ -1082,12 +1124,12 @@ tk_status tk_state_dt(const tk_state* st, int32_t inst, double* dt) {
 namespace {
 
 struct CkptHeader {
-  char magic[8];  // "TKCKPT1"
+  char magic[8];  // "TKCKPT2"
   int32_t N, CS, nc, ninst, mixed, plain, warm, pad;
 };
 
 struct CkptLayout {
-  size_t ip, core, fac, rank, wkeep, f, total;
+  size_t ip, core, fac, rank, wkeep, wvalid, f, total;
 };
 
 CkptLayout ckpt_layout(const tk_state* st) {
@@ -1108,6 +1150,8 @@ CkptLayout ckpt_layout(const tk_state* st) {
     o += nc * 3 * sizeof(int);
     L.wkeep = o;
     o += nc * 3 * N * N * sizeof(double);
+    L.wvalid = o;
+    o += nc * 3 * sizeof(int);
   }
   L.total = o;
   return L;
@@ -1125,7 +1169,7 @@ tk_status tk_state_checkpoint(tk_state* st, void* buf, size_t bytes, size_t* nee
   if (bytes < L.total) return ctx_fail(ctx, TK_EINVAL, "checkpoint buffer too small");
   unsigned char* b = static_cast<unsigned char*>(buf);
   CkptHeader h{};
-  std::memcpy(h.magic, "TKCKPT1", 8);
+  std::memcpy(h.magic, "TKCKPT2", 8);
   h.N = st->N;
   h.CS = st->CS;
   h.nc = st->nc;
@@ -1148,6 +1192,7 @@ tk_status tk_state_checkpoint(tk_state* st, void* buf, size_t bytes, size_t* nee
     if (e == hipSuccess) e = hipMemcpy(b + L.rank, st->rank[st->cur], nc * 3 * sizeof(int), hipMemcpyDeviceToHost);
     if (e == hipSuccess)
       e = hipMemcpy(b + L.wkeep, st->Wkeep, nc * 3 * N * N * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(b + L.wvalid, st->d_wvalid, nc * 3 * sizeof(int), hipMemcpyDeviceToHost);
   }
   return ctx_hip(ctx, e, "checkpoint copy");
 }
@@ -1161,7 +1206,7 @@ tk_status tk_state_restore(tk_state* st, const void* buf, size_t bytes) {
   if (bytes < sizeof(CkptHeader)) return ctx_fail(ctx, TK_EINVAL, "restore: buffer too small");
   CkptHeader h;
   std::memcpy(&h, b, sizeof(h));
-  if (std::memcmp(h.magic, "TKCKPT1", 8) != 0) return ctx_fail(ctx, TK_EINVAL, "restore: not a checkpoint");
+  if (std::memcmp(h.magic, "TKCKPT2", 8) != 0) return ctx_fail(ctx, TK_EINVAL, "restore: not a checkpoint");
   if (h.N != st->N || h.CS != st->CS || h.nc != st->nc || h.ninst != st->ninst || h.mixed != (st->mixed ? 1 : 0) ||
       h.plain != (st->plain ? 1 : 0))
     return ctx_fail(ctx, TK_EINVAL, "restore: checkpoint of a different state shape");
@@ -1185,6 +1230,7 @@ tk_status tk_state_restore(tk_state* st, const void* buf, size_t bytes) {
     if (e == hipSuccess) e = hipMemcpy(st->rank[st->cur], b + L.rank, nc * 3 * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(st->Wkeep, b + L.wkeep, nc * 3 * N * N * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(st->d_wvalid, b + L.wvalid, nc * 3 * sizeof(int), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return ctx_hip(ctx, e, "restore copy");
   // the face coefficients dt A / V carry the checkpoint's dt
@@ -1258,6 +1304,38 @@ tk_status tk_state_streams(tk_state* st, int32_t two, int32_t* available) {
   const bool have = st->X2 && st->q2;
   if (available) *available = have ? 1 : 0;
   if (two >= 0) st->one_stream = two == 0;
+  return TK_OK;
+}
+
+tk_status tk_state_rounding(tk_state* st, int32_t factor_space, int64_t* counts) {
+  if (!st) return TK_EINVAL;
+  tk_ctx* ctx = st->ctx;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  if (factor_space > 0 && !st->d_rlistM)
+    return ctx_fail(ctx, TK_EINVAL, "rounding in factor space needs axis-aligned faces, N <= 32 and a Tucker state");
+  if (factor_space >= 0) {
+    st->rspace = factor_space > 0;
+    // the graphs captured for the other path
+    for (int p = 0; p < 2; ++p) {
+      if (st->gexec[p]) (void)hipGraphExecDestroy(st->gexec[p]);
+      st->gexec[p] = nullptr;
+    }
+  }
+  if (counts) {
+    for (int i = 0; i < 4; ++i) counts[i] = 0;
+    if (st->d_rstats) {
+      unsigned long long v[8];
+      hipError_t e = hipStreamSynchronize(ctx->stream);
+      if (e == hipSuccess) e = hipMemcpy(v, st->d_rstats, sizeof(v), hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemset(st->d_rstats, 0, sizeof(v));
+      if (e != hipSuccess) return ctx_hip(ctx, e, "rounding counters");
+      counts[0] = (int64_t)v[0];
+      counts[1] = (int64_t)v[4];
+      counts[3] = (int64_t)(v[2] + v[6]);
+    }
+    counts[2] = st->dense_total;
+    st->dense_total = 0;
+  }
   return TK_OK;
 }
 

@@ -70,11 +70,15 @@ struct DevState {
   const double* est_core;  // [n_est][kEstCap^3]
   const double* est_fac;   // [n_est][3][kEstCap][N]
   const int* est_rank;     // [n_est][3]
+  // N-basis rounding over a device-side cell list: pass-local cell k is
+  // cells[c0 + k], and a pass ends at *cells_n (nullptr: cells c0 + k)
+  const int* cells;
+  const int* cells_n;
 };
 
 // Kernel families (names used by the profiler interface).
 enum KernelId { KID_MOMENTS = 0, KID_EXPAND, KID_GRAM, KID_EIG, KID_PROJECT, KID_INIT, KID_PLAIN_MOM,
-                KID_PLAIN_STEP, KID_RESID, KID_COUNT };
+                KID_PLAIN_STEP, KID_RESID, KID_RROUND, KID_COUNT };
 extern const char* kKernelNames[KID_COUNT];
 
 // ---- launchers (each enqueues on `s`) -------------------------------------
@@ -84,14 +88,17 @@ hipError_t launch_moments(const DevState& d, hipStream_t s);
 // (device memory for `count` cells and a counter)
 hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixed, int oblique, int* list,
                          int* list_n, hipStream_t s);
-hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hipStream_t s);
+// c0/cells_n: workgroups whose c0 + k reaches *cells_n exit (device-side cell lists)
+hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hipStream_t s, int c0 = 0,
+                       const int* cells_n = nullptr);
 // eig of Grams [count][3][N][N]; writes factors/ranks of cells c0.. into the
 // next buffers (tol/cap per instance via inst/ip, or the overrides when
 // inst == nullptr)
 hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
                       double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
                       const double* Win, double* Wout, double* Wkeep, double rel_thr, double abs_fac,
-                      hipStream_t s, double drop = 0.0, const int* rank_prev = nullptr, int lead = 0);
+                      hipStream_t s, double drop = 0.0, const int* rank_prev = nullptr, int lead = 0,
+                      const int* cells = nullptr, const int* cells_n = nullptr, int* wvalid = nullptr);
 hipError_t eig_stats(unsigned long long* out, bool reset);
 // |xi . e| on the full grid for `count` unit normals (FP64), for the estimate
 hipError_t launch_absxi(int N, int count, const double* normals, double xi_min, double dxi, double* X,
@@ -100,9 +107,19 @@ hipError_t launch_absxi(int N, int count, const double* normals, double xi_min, 
 hipError_t launch_identity_basis(int N, size_t count, double* W, hipStream_t s);
 // Gram of the rotated unfoldings: G2_a = (W_a^T A_(a)) (W_a^T A_(a))^T
 hipError_t launch_gram_rot(int N, int count, const void* X, int mixed, const double* W, double* G2,
-                           hipStream_t s);
+                           hipStream_t s, int c0 = 0, const int* cells_n = nullptr);
 hipError_t launch_project(int N, int count, const void* X, int mixed, int c0, int CS, const double* fac_n,
-                          const int* rank_n, double* core_n, hipStream_t s);
+                          const int* rank_n, double* core_n, hipStream_t s, const int* cells = nullptr,
+                          const int* cells_n = nullptr);
+// Rounding in the space of the concatenated factors, fused with the term
+// assembly (axis-aligned faces): every cell of d in a first tier, the cells
+// it leaves (listM/nM) in a second; the cells left by both go to listD/nD
+// for the N-basis path.  wvalid[3 c + a] = 0 for the cells rounded here.
+// stats (nullable, 8 counters): [0]/[4] cells rounded by tier 1/2, [2]/[6]
+// their Jacobi sweeps.
+hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s);
+hipError_t launch_rround(const DevState& d, int* listM, int* nM, int* listD, int* nD, int* wvalid,
+                         unsigned long long* stats, hipStream_t s);
 // generic expansion of `count` Tucker tensors given in the state layout into X (fp64)
 hipError_t launch_expand_plain(int N, int count, int CS, const double* core, const double* fac,
                                const int* rank, double* X, hipStream_t s);

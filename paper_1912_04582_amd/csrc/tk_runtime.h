@@ -120,6 +120,19 @@ struct tk_state {
   double* d_est_core = nullptr;  // [n_est][6^3]
   double* d_est_fac = nullptr;   // [n_est][3][6][N]
   int* d_est_rank = nullptr;     // [n_est][3]
+  // rounding in the space of the concatenated factors (axis-aligned faces,
+  // N <= 32): its two tiers' hand-off lists and counts, the cells left to
+  // the N-basis passes, per-cell-and-mode validity of the kept N-basis
+  // eigenbases, counters, and a pinned word for the count of the N-basis
+  // cells read back each eager step
+  bool rspace = false;
+  int* d_rlistM = nullptr;
+  int* d_rlistD = nullptr;
+  int* d_rcnt = nullptr;  // [0] second-tier list, [1] N-basis list
+  int* d_wvalid = nullptr;
+  unsigned long long* d_rstats = nullptr;
+  int* h_rcnt = nullptr;
+  long long dense_total = 0;  // cells rounded on the N-basis path (eager steps)
   double* Wb = nullptr;     // first-pass bases of the FP64 refinement
   double* Wkeep = nullptr;  // [nc][3][N][N] previous full eigenbases (warm start)
   bool warm = false;        // Wkeep holds real bases (after the first step)

@@ -26,7 +26,7 @@ EXPORTED = [
     "tk_ctx_create", "tk_ctx_destroy", "tk_last_error", "tk_sync", "tk_prof_enable", "tk_prof_get",
     "tk_prof_reset", "tk_prof_eig", "tk_mesh_load", "tk_mesh_destroy", "tk_state_init", "tk_state_init_batch",
     "tk_state_destroy", "tk_state_info", "tk_state_dt", "tk_state_set_chunk", "tk_state_chunk",
-    "tk_state_tune", "tk_state_use_graph", "tk_state_streams", "tk_state_checkpoint", "tk_state_restore", "tk_moments", "tk_step", "tk_step_async",
+    "tk_state_tune", "tk_state_use_graph", "tk_state_streams", "tk_state_rounding", "tk_state_checkpoint", "tk_state_restore", "tk_moments", "tk_step", "tk_step_async",
     "tk_state_ranks", "tk_state_export", "tk_round_tucker", "tk_round_tucker_noalloc", "tk_plain_init",
     "tk_serve_create",
     "tk_serve_submit", "tk_serve_poll", "tk_serve_destroy",
@@ -107,6 +107,7 @@ def lib():
             "tk_state_tune": [P, C.POINTER(C.c_int32)],
             "tk_state_use_graph": [P, C.c_int32],
             "tk_state_streams": [P, C.c_int32, C.POINTER(C.c_int32)],
+            "tk_state_rounding": [P, C.c_int32, C.POINTER(C.c_int64)],
             "tk_state_checkpoint": [P, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)],
             "tk_state_restore": [P, C.c_void_p, C.c_size_t],
             "tk_moments": [P, C.POINTER(C.c_double)],
@@ -346,6 +347,16 @@ class State:
         av = C.c_int32()
         _check(lib().tk_state_streams(self.h, -1 if two is None else (1 if two else 0), C.byref(av)), self.ctx.h)
         return bool(av.value)
+
+    def rounding(self, factor_space=None):
+        """tk_state_rounding: factor_space True/False selects the rounding
+        path, None leaves it.  Returns (and resets) the counters: cells rounded
+        in factor space by its two layouts, cells rounded in the N-basis by
+        eager steps, Jacobi sweeps in factor space."""
+        v = (C.c_int64 * 4)()
+        fs = -1 if factor_space is None else (1 if factor_space else 0)
+        _check(lib().tk_state_rounding(self.h, fs, v), self.ctx.h)
+        return {"factor_small": v[0], "factor_large": v[1], "nbasis": v[2], "sweeps": v[3]}
 
     def moments(self):
         out = np.zeros((self.n_cells, 8))
