@@ -103,29 +103,43 @@ def measured_traffic(workload_name, fam):
 
 
 def roofline(fam, cfg, mesh, res, steps):
-    """Achieved rate of one kernel family against its bound, per launch."""
+    """Achieved rate of one kernel family against its bound, per launch.
+
+    rround: the FP64 operations the factor-space kernels count for the cells
+    they round (Gram-Schmidt, core assembly, Grams, Jacobi, rotations,
+    outputs; 2 per multiply-add), FP64 vector peak.  N-basis families: the
+    per-cell models above times the cells that took that path in the window."""
     N, nc = cfg["N"], mesh["n_cells"]
     ms, launches = res["prof"][fam]
+    if not launches:
+        return None
     per_launch_s = ms / 1e3 / launches
     launches_per_step = launches / steps
+    rp = res.get("rounding_paths") or {}
+    nb = rp.get("nbasis", nc * steps) / steps  # N-basis cells per step
     r_avg = 0.5 * (res["ranks0"].astype(np.float64) + res["ranks1"].astype(np.float64))
-    if fam == "gram":
-        work, bound, peak, unit = gram_flops(N, nc), "mfma", PEAK["fp64_mfma"], "TFLOP/s"
+    frac_nb = nb / nc
+    if fam == "rround":
+        work, bound, peak, unit = rp.get("flops", 0) / steps, "alu", PEAK["fp64_vec"], "TFLOP/s"
+    elif fam == "gram":
+        work, bound, peak, unit = gram_flops(N, nb), "mfma", PEAK["fp64_mfma"], "TFLOP/s"
     elif fam == "eig":
-        work, bound, peak, unit = eig_flops(N, 3 * nc), "alu", PEAK["fp64_vec"], "TFLOP/s"
+        work, bound, peak, unit = eig_flops(N, 3 * nb), "alu", PEAK["fp64_vec"], "TFLOP/s"
     elif fam == "expand":
-        work = expand_flops(N, r_avg, neighbour_ranks(mesh, r_avg))
+        work = frac_nb * expand_flops(N, r_avg, neighbour_ranks(mesh, r_avg))
         bound, peak, unit = "alu", PEAK["fp32_vec_nopk"], "TFLOP/s"
     elif fam == "project":
-        work, bound, peak, unit = project_flops(N, r_avg), "alu", PEAK["fp64_vec"], "TFLOP/s"
+        work, bound, peak, unit = frac_nb * project_flops(N, r_avg), "alu", PEAK["fp64_vec"], "TFLOP/s"
     else:
         return None
     achieved = work / launches_per_step / per_launch_s / 1e12
     per_cell = measured_traffic(cfg["name"], fam)
-    traffic = per_cell * nc / launches_per_step if per_cell is not None else None
+    cells_per_step = rp.get("factor", 0) / steps if fam == "rround" else nb
+    traffic = per_cell * cells_per_step / launches_per_step if per_cell is not None else None
     return {"bound": bound, "achieved": achieved, "peak": peak / 1e12, "unit": unit,
             "frac": achieved / (peak / 1e12), "traffic": traffic, "kernel": fam,
-            "avg_launch_ms": per_launch_s * 1e3, "launches_per_step": launches_per_step}
+            "avg_launch_ms": per_launch_s * 1e3, "launches_per_step": launches_per_step,
+            "work_per_launch": work / launches_per_step}
 
 
 def has_oblique_faces(mesh):
@@ -151,8 +165,8 @@ def cpu_leg(name, targets, steps):
     """Oracle (O2) dependency cones of `targets` advanced `steps` steps; prints JSON."""
     from oracle import fv, tucker_dvm as td
     cfg, mesh, m0 = workload(name)
+    S = fv.Setup(mesh, cfg, m0)  # mesh tables and dt: set-up, not timed (as on the GPU)
     t0 = time.perf_counter()
-    S = fv.Setup(mesh, cfg, m0)
     levels = td.cone(S, targets, steps)
     st = td.run_cone(S, m0, targets, steps)
     t1 = time.perf_counter()
@@ -162,15 +176,37 @@ def cpu_leg(name, targets, steps):
                       "levels": [len(l) for l in levels]}))
 
 
-def run_cpu_leg(name, targets, steps):
+def run_cpu_leg(name, targets, steps, workers):
+    """The oracle's cones of `targets`, split round-robin over `workers`
+    processes run at the same time (one thread each)."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", "--workload", name,
-           "--targets", ",".join(map(str, targets)), "--leg-steps", str(steps)]
-    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
-    if r.returncode != 0:
-        raise RuntimeError(r.stderr[-2000:])
-    return json.loads(r.stdout.strip().splitlines()[-1])
+    groups = [targets[i::workers] for i in range(workers)]
+    groups = [g for g in groups if g]
+    procs = []
+    for g in groups:
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", "--workload", name,
+               "--targets", ",".join(map(str, g)), "--leg-steps", str(steps)]
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env))
+    out = {"seconds": 0.0, "updates": 0, "macros": {}, "workers": len(procs)}
+    for pr in procs:
+        so, se = pr.communicate(timeout=900)
+        if pr.returncode != 0:
+            raise RuntimeError(se[-2000:])
+        r = json.loads(so.strip().splitlines()[-1])
+        out["seconds"] = max(out["seconds"], r["seconds"])
+        out["updates"] += r["updates"]
+        out["macros"].update(r["macros"])
+    return out
+
+
+def host_cores():
+    """CPU threads this process may use, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def gpu_macros_after(cfg, mesh, m0, steps):
@@ -198,24 +234,34 @@ def macro_rel_err(a, b, Rg=0.5, m=1.0):
     return float(e)
 
 
-def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True, one_stream=False):
+def run_gpu(cfg, mesh, m0, total, window, warmup, plain=False, prof=True, one_stream=False, tune=True):
+    """Advance a state `total` steps from the initial fields and time the
+    last `window` of them (after at least `warmup` untimed steps on the same
+    state).  Pass-size trials run first on a throw-away state."""
+    window = min(window, total)
+    pre = max(warmup, total - window)
     ctx = tk.Context(0)
     try:
         tm = tk.Mesh(ctx, mesh)
-        # untimed: the pass-size trial steps (the choice is kept on the
-        # context for the timed state of the same shape), then the warm-up
-        w = tk.State(ctx, tm, cfg, m0, plain=plain)
-        if one_stream and not plain:
-            w.streams(False)
-        trials = w.tune()
-        if not plain:
-            log(f"  rounding pass: {w.chunk()[0]} cells (of {w.chunk()[1]}), chosen over {trials} steps (16 untimed, then 4 per size)")
-        if warmup:
-            w.step(warmup)
-        w.close()
+        if tune and not plain:
+            # untimed: the pass-size trial steps (the choice is kept on the
+            # context for the timed state of the same shape)
+            w = tk.State(ctx, tm, cfg, m0)
+            if one_stream:
+                w.streams(False)
+            trials = w.tune()
+            log(f"  rounding pass: {w.chunk()[0]} cells (of {w.chunk()[1]}), chosen over {trials} steps")
+            w.close()
         st = tk.State(ctx, tm, cfg, m0, plain=plain)
-        if one_stream and not plain:
-            st.streams(False)
+        two = None
+        if not plain:
+            if one_stream:
+                st.streams(False)
+                two = False
+            else:
+                two = st.streams(None)  # the second stream is used when it exists
+        if pre:
+            st.step(pre)
         ctx.sync()
         ctx.prof_reset()
         ctx.prof_enable(prof)
@@ -224,7 +270,7 @@ def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True, one_stream=Fal
             st.rounding()
         r0 = None if plain else st.ranks()[0]
         t0 = time.perf_counter()
-        st.step(steps)  # waits for completion
+        st.step(window)  # waits for completion
         t1 = time.perf_counter()
         ctx.prof_enable(False)
         fams = ["moments", "rround", "expand", "gram", "eig", "project"] if not plain else ["plain_moments", "plain_step"]
@@ -233,14 +279,16 @@ def run_gpu(cfg, mesh, m0, steps, warmup, plain=False, prof=True, one_stream=Fal
         rcount = None
         if not plain:
             rcount = st.rounding()
-            log(f"  eigensolver: {eig}")
-            log(f"  rounding paths (cell-updates): {rcount}")
+            log(f"  eigensolver (N-basis path): {eig}")
+            log(f"  rounding paths over the window (cell-updates): {rcount}")
         r1, C = (None, None) if plain else st.ranks()
+        final = st.moments()
         st.close()
         tm.close()
     finally:
         ctx.close()
-    return dict(seconds=t1 - t0, prof=prof_ms, ranks0=r0, ranks1=r1, compression=C, rounding_paths=rcount)
+    return dict(seconds=t1 - t0, prof=prof_ms, ranks0=r0, ranks1=r1, compression=C, rounding_paths=rcount,
+                final=final, pre=pre, window=window, two_streams=two)
 
 
 def run_batch(steps, warmup, count, prof_steps=3):
@@ -475,32 +523,33 @@ def main():
     nc = mesh["n_cells"]
     N = cfg["N"]
     oblique = has_oblique_faces(mesh)
-    a.steps = a.steps or int(cfg["steps"])
+    total = int(cfg["steps"])
+    window = min(a.steps or total, total)
     if a.parity_steps is None:
         a.parity_steps = 2 if oblique else 6
     if a.parity_cells is None:
-        a.parity_cells = 4 if oblique else 24
-    log(f"workload {cfg['name']}: {nc} cells, N={N}, cap {cfg['cap']}, tol {cfg['tol']}, {cfg['precision']}")
-    res = run_gpu(cfg, mesh, m0, a.steps, a.warmup, one_stream=a.one_stream)
-    ms_step = 1e3 * res["seconds"] / a.steps
-    value = nc * a.steps / res["seconds"]
-    log(f"tucker: {ms_step:.2f} ms/step, {value:.4g} cell-updates/s, mean compression {res['compression']:.4g}")
+        a.parity_cells = 4 if oblique else 48
+    log(f"workload {cfg['name']}: {nc} cells, N={N}, cap {cfg['cap']}, tol {cfg['tol']}, {cfg['precision']}; "
+        f"{total} steps, the last {window} timed")
+    res = run_gpu(cfg, mesh, m0, total, window, a.warmup, one_stream=a.one_stream)
+    ms_step = 1e3 * res["seconds"] / window
+    value = nc * window / res["seconds"]
+    log(f"tucker: {ms_step:.2f} ms/step over steps {res['pre']}..{res['pre'] + window}, {value:.4g} cell-updates/s, "
+        f"mean compression {res['compression']:.4g}")
     for f, (ms, n) in res["prof"].items():
         log(f"  {f:10s} {ms:10.2f} ms total over {n} launches")
     r1 = res["ranks1"]
     rmax = r1.max(1)
     log("  final max-rank histogram:", np.bincount(rmax, minlength=cfg["cap"] + 1).tolist())
-    nbr = neighbour_ranks(mesh, r1)
-    r0 = 2 * r1.astype(np.int64).sum(1)  # own [U, D U] columns summed over modes
     log(f"  mean rank {r1.mean():.2f}")
     fam, (fms, fn) = max(res["prof"].items(), key=lambda kv: kv[1][0])
-    roof = roofline(fam, cfg, mesh, res, a.steps)
+    roof = roofline(fam, cfg, mesh, res, window)
     log(f"  roofline ({fam}): {roof}")
     plain = None
     if oblique:
         plain = {"value": None, "reason": "the plain comparator covers axis-aligned faces only"}
     elif not a.no_plain:
-        pres = run_gpu(cfg, mesh, m0, a.plain_steps, 1, plain=True)
+        pres = run_gpu(cfg, mesh, m0, a.plain_steps, a.plain_steps, 1, plain=True)
         pv = nc * a.plain_steps / pres["seconds"]
         plain = {"value": pv, "unit": "cell-updates/s", "ms_per_step": 1e3 * pres["seconds"] / a.plain_steps,
                  "steps": a.plain_steps, "storage": "N^3 values per cell",
@@ -509,51 +558,62 @@ def main():
     cpu = parity = None
     if not a.no_cpu:
         targets = sample_targets(mesh, a.parity_cells)
-        leg = run_cpu_leg(a.workload, targets, a.parity_steps)
-        cpu = {"value": leg["updates"] / leg["seconds"], "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+        workers = host_cores()
+        leg = run_cpu_leg(a.workload, targets, a.parity_steps, workers)
+        cpu = {"value": leg["updates"] / leg["seconds"], "unit": "cell-updates/s", "cores": leg["workers"],
+               "kind": "oracle",
                "sample": f"Tucker-form oracle, dependency cones of {len(targets)} cells advanced "
-                         f"{a.parity_steps} steps from the initial state ({leg['updates']} cell-updates, "
-                         f"{leg['seconds']:.1f} s, one thread)"}
+                         f"{a.parity_steps} steps from the initial state, split over {leg['workers']} "
+                         f"single-thread processes ({leg['updates']} cell-updates, {leg['seconds']:.1f} s "
+                         f"for the slowest process)"}
         g = gpu_macros_after(cfg, mesh, m0, a.parity_steps)
         ref = np.array([leg["macros"][str(t)] for t in targets])
         err = macro_rel_err(g[targets], ref)
         bar = 1e-5 if cfg["precision"] == "mixed" else 1e-10
         parity = {"max_rel_err": err, "bar": bar, "pass": bool(err <= bar), "cells": targets,
                   "steps": a.parity_steps}
-        log(f"cpu oracle: {cpu['value']:.4g} cell-updates/s; parity after {a.parity_steps} steps: {err:.3e}")
-    end = None
+        log(f"cpu oracle: {cpu['value']:.4g} cell-updates/s on {leg['workers']} processes; "
+            f"parity after {a.parity_steps} steps: {err:.3e}")
+    end = fp64 = None
     if cfg["precision"] == "mixed" and not a.no_fp64_check and N <= 32:
-        # The mixed path against the FP64 path (itself pinned to the oracle)
-        # at the end of the timed run, beside the spread of the FP64 path
-        # when only the truncation tolerance moves by 1%: once a singular
-        # value sits at the truncation threshold, either rank is a valid
-        # truncation, and that spread is the floor any two implementations
-        # can be held to.
+        # The FP64 path on the same window (timed), the mixed path against it
+        # at the end of the run, and the FP64 path's own spread when its
+        # inputs move by 1e-7 relative (the oracle's noise floor under an
+        # FP32-sized perturbation)
         c64 = dict(cfg, precision="fp64")
-        g64 = gpu_macros_after(c64, mesh, m0, a.steps)
-        gmx = gpu_macros_after(cfg, mesh, m0, a.steps)
-        g64b = gpu_macros_after(dict(c64, tol=1.01 * cfg["tol"]), mesh, m0, a.steps)
-        e_end = macro_rel_err(gmx, g64)
-        floor = macro_rel_err(g64b, g64)
-        end = {"steps": a.steps, "max_rel_err_mixed_vs_fp64": e_end,
-               "max_rel_err_fp64_tol_x1.01_vs_fp64": floor, "bar": 1e-5, "within_bar": bool(e_end <= 1e-5),
-               "ratio_to_tolerance_floor": e_end / floor if floor > 0 else None}
-        log(f"end of run: mixed vs FP64 path after {a.steps} steps: {e_end:.3e} "
-            f"(FP64 with tolerance x1.01 vs FP64: {floor:.3e})")
+        r64 = run_gpu(c64, mesh, m0, total, window, a.warmup, prof=False, one_stream=a.one_stream)
+        fp64 = {"value": nc * window / r64["seconds"], "unit": "cell-updates/s",
+                "ms_per_step": 1e3 * r64["seconds"] / window, "steps": window}
+        log(f"fp64 path: {fp64['ms_per_step']:.2f} ms/step, {fp64['value']:.4g} cell-updates/s")
+        rng = np.random.default_rng(7)
+        mp = m0.copy()
+        mp[:, 0] *= 1.0 + 1e-7 * rng.standard_normal(nc)
+        mp[:, 1:4] += 1e-7 * np.sqrt(mp[:, 4:5]) * rng.standard_normal((nc, 3))
+        mp[:, 4] *= 1.0 + 1e-7 * rng.standard_normal(nc)
+        g64p = gpu_macros_after(c64, mesh, mp, total)
+        e_end = macro_rel_err(res["final"], r64["final"])
+        floor = macro_rel_err(g64p, r64["final"])
+        end = {"steps": total, "max_rel_err_mixed_vs_fp64": e_end,
+               "fp64_input_perturbation_1e-7_spread": floor, "bar": 1e-5, "within_bar": bool(e_end <= 1e-5)}
+        log(f"end of run: mixed vs FP64 path after {total} steps: {e_end:.3e} "
+            f"(FP64 with inputs perturbed by 1e-7: {floor:.3e})")
     out = {
-        "metric": "Tucker S-model cell-updates/s (vs plain GPU step at 1e-5 rel err)",
-        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "metric": "Tucker S-model cell-updates/s vs plain GPU step; macro error vs the FP64 path stated",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": window, "warmup": res["pre"],
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 terms + f64 rounding" if cfg["precision"] == "mixed" else "f64",
+        "dtype": "f64 factor-space rounding, f32 N-basis terms" if cfg["precision"] == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "cells": nc, "N": N, "rank_cap": cfg["cap"], "tol": cfg["tol"],
-                   "precision": cfg["precision"], "steps_from_init": a.steps,
-                   "rounding_streams": 1 if a.one_stream else 2},
+                   "precision": cfg["precision"], "run_steps": total,
+                   "timed_window": [res["pre"], res["pre"] + window],
+                   "rounding_streams": 2 if res["two_streams"] else 1},
         "dominant_kernel": fam,
-        "kernel_ms_per_step": {f: ms / a.steps for f, (ms, n) in res["prof"].items()},
+        "kernel_ms_per_step": {f: ms / window for f, (ms, n) in res["prof"].items()},
+        "rounding_paths_per_step": {k: v / window for k, v in (res["rounding_paths"] or {}).items()},
         "mean_compression": res["compression"],
         "roofline": roof,
         "plain_gpu": plain,
+        "fp64_path": fp64,
         "cpu_baseline": cpu,
         "parity": parity,
         "end_of_run": end,

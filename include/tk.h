@@ -192,20 +192,22 @@ tk_status tk_state_use_graph(tk_state* st, int32_t on);
 tk_status tk_state_streams(tk_state* st, int32_t two, int32_t* available);
 /* Rounding path (Op4, Section "Tensor decompositions").  With
  * factor_space = 1 (the default where available: every face on a
- * coordinate axis and N <= 32) each cell's update is rounded in the space
- * of its concatenated factors: Gram-Schmidt QR of the factors, the small
- * core multiplied by the R factors, eigen-decompositions of that core's
- * unfolding Grams, fused with the term assembly; cells whose concatenated
- * ranks or core exceed that path's layouts are rounded in the N-basis
- * (the update expanded on the N^3 grid, mode Grams of the full tensor).
+ * coordinate axis and N <= 32) a cell whose own state and far sides all
+ * have rank 1 is rounded in the space of its concatenated factors:
+ * Gram-Schmidt QR of the factors, the small core multiplied by the R
+ * factors, eigen-decompositions of that core's unfolding Grams, fused with
+ * the term assembly; the other cells are rounded in the N-basis (the update
+ * expanded on the N^3 grid, mode Grams of the full tensor).
  * factor_space = 0 rounds every cell in the N-basis; < 0 leaves the
  * setting.  Both give the truncated HOSVD of the same update (results
  * differ by rounding errors, and where an eigenvalue sits at the
  * truncation threshold by the rank chosen).  TK_EINVAL when enabling it on
  * a state without the factor-space path.  counts (nullable, [4]) receives
- * and resets: cells rounded in factor space by its first (small) and
- * second layout, cells rounded in the N-basis by eager steps, and Jacobi
- * sweeps in factor space.  Waits for the context stream.                 */
+ * and resets: cells rounded in factor space, cells rounded in the N-basis
+ * by eager steps, Jacobi sweeps in factor space, and the FP64 operations
+ * of the factor-space rounding (2 per multiply-add of its Gram-Schmidt,
+ * core, Gram, rotation, Jacobi and output products).  Waits for the
+ * context stream.                                                         */
 tk_status tk_state_rounding(tk_state* st, int32_t factor_space, int64_t* counts);
 
 /* Restart checkpoints (Sec. "The program": a run is continued from a saved

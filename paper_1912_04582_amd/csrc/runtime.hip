@@ -542,11 +542,11 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     ALLOC(Wkeep, double, (size_t)nc * 3 * N * N);
     ALLOC(d_wvalid, int, (size_t)nc * 3);
     ALLOC(d_rstats, unsigned long long, 8);
-    S->rspace = !oblique && N <= 32;
-    if (S->rspace) {
-      ALLOC(d_rlistM, int, nc);
+    S->rspace_ok = !oblique && N <= 32;
+    S->rspace = S->rspace_ok;
+    if (S->rspace_ok) {
       ALLOC(d_rlistD, int, nc);
-      ALLOC(d_rcnt, int, 2);
+      ALLOC(d_rcnt, int, 1);
       if (hipHostMalloc((void**)&S->h_rcnt, sizeof(int), 0) != hipSuccess) {
         S->h_rcnt = nullptr;
         state_free(S);
@@ -748,18 +748,20 @@ static tk_status state_step_once(tk_state* st) {
   int dense_n = st->nc;
   if (st->rspace) {
     prof_begin(ctx, KID_RROUND, &ev);
-    e = launch_rround(d, st->d_rlistM, st->d_rcnt, st->d_rlistD, st->d_rcnt + 1, st->d_wvalid, st->d_rstats, q);
+    e = launch_rround(d, st->d_rlistD, st->d_rcnt, st->d_wvalid, st->d_rstats, q);
     prof_end(ctx, KID_RROUND, ev);
     if (e != hipSuccess) return ctx_hip(ctx, e, "rounding in factor space");
     d.cells = st->d_rlistD;
-    d.cells_n = st->d_rcnt + 1;
+    d.cells_n = st->d_rcnt;
     if (!st->capturing) {
-      e = hipMemcpyAsync(st->h_rcnt, st->d_rcnt + 1, sizeof(int), hipMemcpyDeviceToHost, q);
+      e = hipMemcpyAsync(st->h_rcnt, st->d_rcnt, sizeof(int), hipMemcpyDeviceToHost, q);
       if (e == hipSuccess) e = hipStreamSynchronize(q);
       if (e != hipSuccess) return ctx_hip(ctx, e, "rounding list count");
       dense_n = *st->h_rcnt;
       st->dense_total += dense_n;
     }
+  } else if (!st->capturing) {
+    st->dense_total += st->nc;
   }
   // odd passes on the second stream with the second workspace: the passes
   // are independent (each reads the current state and writes its own cells
@@ -1311,7 +1313,7 @@ tk_status tk_state_rounding(tk_state* st, int32_t factor_space, int64_t* counts)
   if (!st) return TK_EINVAL;
   tk_ctx* ctx = st->ctx;
   std::lock_guard<std::recursive_mutex> g(ctx->mu);
-  if (factor_space > 0 && !st->d_rlistM)
+  if (factor_space > 0 && !st->rspace_ok)
     return ctx_fail(ctx, TK_EINVAL, "rounding in factor space needs axis-aligned faces, N <= 32 and a Tucker state");
   if (factor_space >= 0) {
     st->rspace = factor_space > 0;
@@ -1330,10 +1332,10 @@ tk_status tk_state_rounding(tk_state* st, int32_t factor_space, int64_t* counts)
       if (e == hipSuccess) e = hipMemset(st->d_rstats, 0, sizeof(v));
       if (e != hipSuccess) return ctx_hip(ctx, e, "rounding counters");
       counts[0] = (int64_t)v[0];
-      counts[1] = (int64_t)v[4];
-      counts[3] = (int64_t)(v[2] + v[6]);
+      counts[2] = (int64_t)v[2];
+      counts[3] = (int64_t)v[1];
     }
-    counts[2] = st->dense_total;
+    counts[1] = st->dense_total;
     st->dense_total = 0;
   }
   return TK_OK;

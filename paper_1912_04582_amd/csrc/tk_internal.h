@@ -112,14 +112,15 @@ hipError_t launch_project(int N, int count, const void* X, int mixed, int c0, in
                           const int* rank_n, double* core_n, hipStream_t s, const int* cells = nullptr,
                           const int* cells_n = nullptr);
 // Rounding in the space of the concatenated factors, fused with the term
-// assembly (axis-aligned faces): every cell of d in a first tier, the cells
-// it leaves (listM/nM) in a second; the cells left by both go to listD/nD
-// for the N-basis path.  wvalid[3 c + a] = 0 for the cells rounded here.
-// stats (nullable, 8 counters): [0]/[4] cells rounded by tier 1/2, [2]/[6]
-// their Jacobi sweeps.
+// assembly (axis-aligned faces, rank-1 neighbourhoods): every cell of d is
+// tried; the cells it leaves go to listD/nD for the N-basis path.
+// wvalid[3 c + a] = 0 for the cells rounded here.  stats (nullable, 8
+// counters): [0] cells rounded, [1] their FP64 operations, [2] their Jacobi
+// sweeps.
+hipError_t launch_rround(const DevState& d, int* listD, int* nD, int* wvalid, unsigned long long* stats,
+                         hipStream_t s);
+// p[0..n) = v
 hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s);
-hipError_t launch_rround(const DevState& d, int* listM, int* nM, int* listD, int* nD, int* wvalid,
-                         unsigned long long* stats, hipStream_t s);
 // generic expansion of `count` Tucker tensors given in the state layout into X (fp64)
 hipError_t launch_expand_plain(int N, int count, int CS, const double* core, const double* fac,
                                const int* rank, double* X, hipStream_t s);

@@ -121,14 +121,13 @@ struct tk_state {
   double* d_est_fac = nullptr;   // [n_est][3][6][N]
   int* d_est_rank = nullptr;     // [n_est][3]
   // rounding in the space of the concatenated factors (axis-aligned faces,
-  // N <= 32): its two tiers' hand-off lists and counts, the cells left to
-  // the N-basis passes, per-cell-and-mode validity of the kept N-basis
-  // eigenbases, counters, and a pinned word for the count of the N-basis
-  // cells read back each eager step
+  // N <= 32): the cells it leaves to the N-basis passes and their count,
+  // per-cell-and-mode validity of the kept N-basis eigenbases, counters,
+  // and a pinned word for that count, read back each eager step
   bool rspace = false;
-  int* d_rlistM = nullptr;
+  bool rspace_ok = false;  // the state supports it
   int* d_rlistD = nullptr;
-  int* d_rcnt = nullptr;  // [0] second-tier list, [1] N-basis list
+  int* d_rcnt = nullptr;
   int* d_wvalid = nullptr;
   unsigned long long* d_rstats = nullptr;
   int* h_rcnt = nullptr;

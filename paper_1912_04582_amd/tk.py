@@ -351,12 +351,12 @@ class State:
     def rounding(self, factor_space=None):
         """tk_state_rounding: factor_space True/False selects the rounding
         path, None leaves it.  Returns (and resets) the counters: cells rounded
-        in factor space by its two layouts, cells rounded in the N-basis by
-        eager steps, Jacobi sweeps in factor space."""
+        in factor space, cells rounded in the N-basis by eager steps, Jacobi
+        sweeps and FP64 operations in factor space."""
         v = (C.c_int64 * 4)()
         fs = -1 if factor_space is None else (1 if factor_space else 0)
         _check(lib().tk_state_rounding(self.h, fs, v), self.ctx.h)
-        return {"factor_small": v[0], "factor_large": v[1], "nbasis": v[2], "sweeps": v[3]}
+        return {"factor": v[0], "nbasis": v[1], "sweeps": v[2], "flops": v[3]}
 
     def moments(self):
         out = np.zeros((self.n_cells, 8))

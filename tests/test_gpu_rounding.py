@@ -1,0 +1,118 @@
+"""The two rounding paths of the step against the FP64 oracle, through the C
+ABI: rounding in the space of the concatenated factors (Op4 as QR of the
+factors, core x R, SVD of the small core) and the N-basis rounding of the
+cells it leaves, on a channel whose cells use both paths within a few steps
+(rank-1 free stream far from the obstacle, higher ranks near it, random
+initial states in half of the cases)."""
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import macro_rel_err
+from oracle import fv, tucker_dvm as td
+from paper_1912_04582_amd import tk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tk.Context(0)
+    yield c
+    c.close()
+
+
+def channel(N, cap, tol, precision, init):
+    m = synth.channel_with_obstacle(nx=8, ny=4, nz=4, h=0.25, obstacle=((3, 5), (1, 3), (1, 3)),
+                                    inflow=(1.0, (0.9, 0.0, 0.0), 1.0), Tw=1.4)
+    cfg = dict(N=N, xi_max=4.5, cap=cap, tol=tol, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=0.1, Rg=0.5, m=1.0,
+               seed=21, init=init, precision=precision)
+    return m, cfg, synth.initial_macros(cfg, m)
+
+
+def oracle_macros(S, states):
+    return np.array([td.macros_of(S, states[i]) for i in range(S.mesh["n_cells"])])
+
+
+CASES = [
+    # N, cap, tol, precision, init, steps, bar, paths that must occur.  From
+    # random states the ranks grow above 1 after one step; the free stream
+    # keeps rank 1 away from the obstacle and grows it near.
+    (16, 6, 1e-6, "fp64", "random", 4, 1e-10, ("factor", "nbasis")),
+    (32, 12, 1e-5, "fp64", "freestream", 4, 1e-10, ("factor", "nbasis")),
+    (24, 8, 1e-6, "fp64", "freestream", 5, 1e-10, ("factor", "nbasis")),
+    (24, 8, 1e-6, "fp64", "random", 3, 1e-10, ("factor", "nbasis")),
+    (32, 12, 1e-5, "mixed", "random", 3, 1e-5, ("factor", "nbasis")),
+    (32, 12, 1e-5, "mixed", "freestream", 4, 1e-5, ("factor", "nbasis")),
+]
+
+
+@pytest.mark.parametrize("N,cap,tol,precision,init,steps,bar,paths", CASES)
+def test_factor_space_rounding_matches_oracle(ctx, N, cap, tol, precision, init, steps, bar, paths):
+    m, cfg, m0 = channel(N, cap, tol, precision, init)
+    mesh = tk.Mesh(ctx, m)
+    st = tk.State(ctx, mesh, cfg, m0)
+    st.rounding()  # reset the counters
+    counts = {"factor": 0, "nbasis": 0}
+    for _ in range(steps):
+        st.step(1)
+        c = st.rounding()
+        for k in counts:
+            counts[k] += c[k]
+    got = st.moments()
+    ranks = st.ranks()[0]
+    st.close()
+    mesh.close()
+    S = fv.Setup(m, cfg, m0)
+    ref_states = td.run(S, m0, steps)
+    err, _ = macro_rel_err(got, oracle_macros(S, ref_states))
+    oranks = np.array([ref_states[i].ranks for i in range(m["n_cells"])])
+    print(f"N={N} {precision} {init}: paths {counts}, max rel macro err {err:.3e}, "
+          f"rank mismatches {(ranks != oranks).any(1).sum()}")
+    assert sum(counts.values()) == steps * m["n_cells"]
+    for p in paths:
+        assert counts[p] > 0, (p, counts)
+    assert err < bar, err
+    if precision == "fp64":
+        assert (ranks == oranks).all()
+
+
+def test_both_paths_reach_the_same_rounding(ctx):
+    """The factor-space and N-basis paths on the same state: the same ranks
+    and macroparameters within the FP64 bar after a few steps, also after
+    switching each state to the other path."""
+    m, cfg, m0 = channel(16, 6, 1e-6, "fp64", "random")
+    mesh = tk.Mesh(ctx, m)
+    a = tk.State(ctx, mesh, cfg, m0)
+    b = tk.State(ctx, mesh, cfg, m0)
+    b.rounding(False)
+    a.step(3)
+    b.step(3)
+    assert b.rounding()["factor"] == 0
+    ra, rb = a.ranks()[0], b.ranks()[0]
+    assert (ra == rb).all()
+    err, _ = macro_rel_err(a.moments(), b.moments())
+    assert err < 1e-10, err
+    # switching the same state between paths keeps it on the same solution
+    a.rounding(False)
+    b.rounding(True)
+    a.step(2)
+    b.step(2)
+    err, _ = macro_rel_err(a.moments(), b.moments())
+    assert err < 1e-10, err
+    a.close(); b.close(); mesh.close()
+
+
+def test_rounding_path_needs_axis_faces(ctx):
+    m = synth.jittered_box(4, 3, 3, 0.25, seed=1)
+    cfg = dict(synth.make_config("cfg0"), N=16, cap=4, tol=1e-5)
+    m0 = synth.initial_macros(cfg, m)
+    mesh = tk.Mesh(ctx, m)
+    st = tk.State(ctx, mesh, cfg, m0)
+    with pytest.raises(tk.TkError) as e:
+        st.rounding(True)
+    assert e.value.status == tk.TK_EINVAL
+    st.step(1)
+    assert st.rounding()["nbasis"] == m["n_cells"]
+    st.close(); mesh.close()
