@@ -94,7 +94,7 @@ enum { TK_FP64 = 0, TK_MIXED = 1 };
  * velocity method"): N uniform nodes per axis on [-xi_max, xi_max] with
  * the end points included, quadrature weight dxi^3.                       */
 typedef struct {
-  int32_t N;          /* 16, 24, 32 or 48                                  */
+  int32_t N;          /* 16, 24, 32, or 48 on the TK_MIXED path only        */
   double xi_max;
   double R_g, m;      /* gas constant, molecular mass                      */
   double Pr;          /* Prandtl number (2/3 for a monatomic gas)          */
@@ -125,6 +125,23 @@ typedef struct {
  * (NULL = the library creates one at default priority).  TK_EDEVICE if the
  * device is not available.                                                */
 tk_status tk_ctx_create(int32_t device, size_t hbm_budget, void* hip_stream, tk_ctx** out);
+/* Device memory from the caller, for example a framework's caching
+ * allocator: every device buffer of the context (states, workspaces, the
+ * rounding hook's buffers) is obtained by alloc(user, bytes), which returns
+ * device memory on `device` aligned to at least 256 bytes or NULL (the call
+ * then fails with TK_ENOMEM), and returned by free(user, ptr) when the
+ * library no longer needs it (at the latest when its state or context is
+ * destroyed).  The budget still applies.  The functions are called with the
+ * context's lock held, from the calling thread (or the server's worker
+ * thread for a serving context) and must not call back into the library.
+ * tk_ctx_create(...) is tk_ctx_create_ex(..., NULL, ...).                  */
+typedef struct {
+  void* user;
+  void* (*alloc)(void* user, size_t bytes);
+  void (*free)(void* user, void* ptr);
+} tk_alloc_fns;
+tk_status tk_ctx_create_ex(int32_t device, size_t hbm_budget, void* hip_stream, const tk_alloc_fns* alloc,
+                           tk_ctx** out);
 tk_status tk_ctx_destroy(tk_ctx* ctx);
 const char* tk_last_error(const tk_ctx* ctx);
 tk_status tk_sync(tk_ctx* ctx);
@@ -252,6 +269,16 @@ tk_status tk_state_ranks(tk_state* st, int32_t* ranks /* [n_cells][3] or NULL */
 /* Copy one cell's Tucker state out (columns beyond the ranks are not
  * written).                                                               */
 tk_status tk_state_export(tk_state* st, int32_t cell, tk_tucker* out);
+
+/* Op4 on a resident state: every cell's current Tucker tensor is rounded
+ * again by truncated HOSVD with tolerance tol and rank cap `cap` (1 .. the
+ * state's rank cap), in FP64 on the N-basis path (the tensor expanded on
+ * the N^3 grid, mode Grams, two Jacobi passes), and becomes the state.  The
+ * step's own rounding is unchanged (it keeps each instance's tol and cap).
+ * Allocates a work space for passes of up to 4096 cells within the budget
+ * (TK_ENOMEM if none fits) and waits for the context stream.  TK_EINVAL for
+ * a plain state, N = 48, tol < 0 or cap out of range.                       */
+tk_status tk_round(tk_state* st, double tol, int32_t cap);
 
 /* Test hook for Op4: round `count` Tucker tensors (same N, ranks <= N)
  * with tolerance tol and rank cap `cap` by truncated HOSVD on the device,

@@ -80,10 +80,18 @@ void* ctx_alloc(tk_ctx* ctx, size_t bytes, tk_status* st) {
     return nullptr;
   }
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    *st = ctx_hip(ctx, e, "hipMalloc");
-    return nullptr;
+  if (ctx->alloc.alloc) {
+    p = ctx->alloc.alloc(ctx->alloc.user, bytes);
+    if (!p) {
+      *st = ctx_fail(ctx, TK_ENOMEM, "the caller's allocator returned no memory for " + std::to_string(bytes) + " bytes");
+      return nullptr;
+    }
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      *st = ctx_hip(ctx, e, "hipMalloc");
+      return nullptr;
+    }
   }
   ctx->used += bytes;
   ctx->sizes[p] = bytes;
@@ -97,7 +105,8 @@ void ctx_free(tk_ctx* ctx, void* p) {
     ctx->used -= it->second;
     ctx->sizes.erase(it);
   }
-  (void)hipFree(p);
+  if (ctx->alloc.alloc) ctx->alloc.free(ctx->alloc.user, p);
+  else (void)hipFree(p);
 }
 
 void prof_begin(tk_ctx* ctx, int kid, hipEvent_t* ev, hipStream_t q = nullptr) {
@@ -966,7 +975,13 @@ tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag) {
 extern "C" {
 
 tk_status tk_ctx_create(int32_t device, size_t hbm_budget, void* hip_stream, tk_ctx** out) {
+  return tk_ctx_create_ex(device, hbm_budget, hip_stream, nullptr, out);
+}
+
+tk_status tk_ctx_create_ex(int32_t device, size_t hbm_budget, void* hip_stream, const tk_alloc_fns* alloc,
+                           tk_ctx** out) {
   if (!out) return TK_EINVAL;
+  if (alloc && (!alloc->alloc || !alloc->free)) return TK_EINVAL;
   *out = nullptr;
   if (device == -1) {
     // host-only context: mesh loading and validation, no device work
@@ -984,6 +999,7 @@ tk_status tk_ctx_create(int32_t device, size_t hbm_budget, void* hip_stream, tk_
   if (hipMemGetInfo(&freeb, &total) != hipSuccess) return TK_EDEVICE;
   c->budget = hbm_budget ? hbm_budget : (size_t)(0.9 * (double)freeb);
   if (scratch_lookup(device, &c->scratch) != hipSuccess) return TK_EDEVICE;
+  if (alloc) c->alloc = *alloc;
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
     c->own_stream = false;
@@ -1503,6 +1519,61 @@ tk_status tk_round_tucker(tk_ctx* ctx, int32_t count, const tk_tucker* in, doubl
       for (int c = 0; c < t.r[a]; ++c)
         for (int i = 0; i < N; ++i) t.U[a][i + N * c] = fo[(((size_t)k * 3 + a) * CSo + c) * N + i];
   }
+  return TK_OK;
+}
+
+tk_status tk_round(tk_state* st, double tol, int32_t cap) {
+  if (!st) return TK_EINVAL;
+  tk_ctx* ctx = st->ctx;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  if (st->plain) return ctx_fail(ctx, TK_EINVAL, "round: a plain state has no Tucker form");
+  const int N = st->N, CS = st->CS;
+  if (N > 32) return ctx_fail(ctx, TK_EINVAL, "round: N must be 16, 24 or 32");
+  if (!(tol >= 0) || cap < 1 || cap > CS) return ctx_fail(ctx, TK_EINVAL, "round: tol must be >= 0 and cap in 1..the storage cap");
+  // passes of cells whose FP64 work space (N^3 tensor, three Grams, three
+  // first-pass bases) fits half of what the budget leaves, at most 4096
+  const size_t nn = (size_t)N * N;
+  const size_t per = sizeof(double) * (nn * N + 6 * nn);
+  const size_t avail = ctx->budget > ctx->used ? ctx->budget - ctx->used : 0;
+  const int pass = (int)std::min<size_t>({(size_t)st->nc, avail / 2 / per, (size_t)4096});
+  if (pass < 1) return ctx_fail(ctx, TK_ENOMEM, "round: no room for the work space");
+  tk_status s = TK_OK;
+  double* X = (double*)ctx_alloc(ctx, (size_t)pass * nn * N * sizeof(double), &s);
+  double* G = X ? (double*)ctx_alloc(ctx, (size_t)pass * 3 * nn * sizeof(double), &s) : nullptr;
+  double* W = G ? (double*)ctx_alloc(ctx, (size_t)pass * 3 * nn * sizeof(double), &s) : nullptr;
+  if (!W) {
+    ctx_free(ctx, X);
+    ctx_free(ctx, G);
+    return s;
+  }
+  hipStream_t q = ctx->stream;
+  const double* core = st->core[st->cur];
+  const double* fac = st->fac[st->cur];
+  const int* rank = st->rank[st->cur];
+  double* core_n = st->core[st->cur ^ 1];
+  double* fac_n = st->fac[st->cur ^ 1];
+  int* rank_n = st->rank[st->cur ^ 1];
+  const size_t c3 = (size_t)CS * CS * CS, cf = (size_t)3 * CS * N;
+  hipError_t e = hipSuccess;
+  for (int c0 = 0; c0 < st->nc && e == hipSuccess; c0 += pass) {
+    const int n = std::min(pass, st->nc - c0);
+    e = launch_expand_plain(N, n, CS, core + c0 * c3, fac + c0 * cf, rank + 3 * (size_t)c0, X, q);
+    if (e == hipSuccess) e = launch_gram(N, n, X, 0, G, q);
+    if (e == hipSuccess)
+      e = launch_eig(N, n, G, nullptr, nullptr, 0, tol, cap, CS, fac_n + c0 * cf, rank_n + 3 * (size_t)c0, nullptr,
+                     W, nullptr, 1e-15, 1e-18, q);
+    if (e == hipSuccess) e = launch_gram_rot(N, n, X, 0, W, G, q);
+    if (e == hipSuccess)
+      e = launch_eig(N, n, G, nullptr, nullptr, 0, tol, cap, CS, fac_n + c0 * cf, rank_n + 3 * (size_t)c0, W,
+                     nullptr, nullptr, 1e-15, 1e-18, q);
+    if (e == hipSuccess) e = launch_project(N, n, X, 0, 0, CS, fac_n + c0 * cf, rank_n + 3 * (size_t)c0, core_n + c0 * c3, q);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(q);
+  ctx_free(ctx, X);
+  ctx_free(ctx, G);
+  ctx_free(ctx, W);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "round");
+  st->cur ^= 1;
   return TK_OK;
 }
 

@@ -13,6 +13,8 @@ struct tk_ctx {
   size_t budget = 0;
   size_t used = 0;
   std::map<void*, size_t> sizes;
+  // device memory from the caller's allocator (alloc.alloc == nullptr: hipMalloc)
+  tk_alloc_fns alloc = {nullptr, nullptr, nullptr};
   // device address of this device's copy of the no-allocation rounding
   // scratch array (runtime.hip), looked up once per device at context set-up
   void* scratch = nullptr;

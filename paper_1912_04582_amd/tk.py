@@ -27,7 +27,8 @@ EXPORTED = [
     "tk_prof_reset", "tk_prof_eig", "tk_mesh_load", "tk_mesh_destroy", "tk_state_init", "tk_state_init_batch",
     "tk_state_destroy", "tk_state_info", "tk_state_dt", "tk_state_set_chunk", "tk_state_chunk",
     "tk_state_tune", "tk_state_use_graph", "tk_state_streams", "tk_state_rounding", "tk_state_checkpoint", "tk_state_restore", "tk_moments", "tk_step", "tk_step_async",
-    "tk_state_ranks", "tk_state_export", "tk_round_tucker", "tk_round_tucker_noalloc", "tk_plain_init",
+    "tk_state_ranks", "tk_state_export", "tk_round", "tk_round_tucker", "tk_round_tucker_noalloc",
+    "tk_plain_init", "tk_ctx_create_ex",
     "tk_serve_create",
     "tk_serve_submit", "tk_serve_poll", "tk_serve_destroy",
 ]
@@ -61,6 +62,14 @@ class tk_params(C.Structure):
 class tk_tucker(C.Structure):
     _fields_ = [("N", C.c_int32), ("r", C.c_int32 * 3), ("core", C.POINTER(C.c_double)),
                 ("U", C.POINTER(C.c_double) * 3)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class tk_alloc_fns(C.Structure):
+    _fields_ = [("user", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
 
 
 class tk_request(C.Structure):
@@ -117,6 +126,8 @@ def lib():
             "tk_state_export": [P, C.c_int32, C.POINTER(tk_tucker)],
             "tk_round_tucker": [P, C.c_int32, C.POINTER(tk_tucker), C.c_double, C.c_int32,
                                 C.POINTER(tk_tucker)],
+            "tk_round": [P, C.c_double, C.c_int32],
+            "tk_ctx_create_ex": [C.c_int32, C.c_size_t, P, C.POINTER(tk_alloc_fns), C.POINTER(P)],
             "tk_round_tucker_noalloc": [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_int32,
                                         P, P, P],
             "tk_serve_create": [P, C.c_size_t, C.POINTER(P)],
@@ -180,9 +191,17 @@ class _MeshArrays:
 
 
 class Context:
-    def __init__(self, device=0, budget=0, stream=None):
+    def __init__(self, device=0, budget=0, stream=None, alloc=None):
+        """alloc: optional (alloc(nbytes) -> device address, free(address))
+        pair of Python callables used for every device buffer (tk_ctx_create_ex)."""
         h = C.c_void_p()
-        _check(lib().tk_ctx_create(int(device), int(budget), stream, C.byref(h)))
+        if alloc is None:
+            _check(lib().tk_ctx_create(int(device), int(budget), stream, C.byref(h)))
+        else:
+            fa, ff = alloc
+            self._alloc = tk_alloc_fns(None, ALLOC_FN(lambda user, n: fa(n) or None),
+                                       FREE_FN(lambda user, p: ff(p)))
+            _check(lib().tk_ctx_create_ex(int(device), int(budget), stream, C.byref(self._alloc), C.byref(h)))
         self.h = h
 
     def close(self):
@@ -357,6 +376,10 @@ class State:
         fs = -1 if factor_space is None else (1 if factor_space else 0)
         _check(lib().tk_state_rounding(self.h, fs, v), self.ctx.h)
         return {"factor": v[0], "nbasis": v[1], "sweeps": v[2], "flops": v[3]}
+
+    def round(self, tol, cap):
+        """tk_round: round every cell of the state again (FP64, N-basis)."""
+        _check(lib().tk_round(self.h, float(tol), int(cap)), self.ctx.h)
 
     def moments(self):
         out = np.zeros((self.n_cells, 8))
