@@ -278,9 +278,12 @@ __device__ int jacobi_wave(double* A, int lda, double* V, int ldv, int nv, int n
 }
 
 // Descending order of n <= 64 values d[0..n) (stable on ties) into order[],
-// by one wavefront.
+// by one wavefront; the identity first, so that every entry stays a valid
+// index even when comparisons fail (non-finite values).
 __device__ inline void sort_desc_wave(const double* d, int stride, int n, int* order) {
   const int lane = threadIdx.x & 63;
+  if (lane < n) order[lane] = lane;
+  wave_sync();
   if (lane < n) {
     const double li = d[lane * stride];
     int pos = 0;
@@ -288,7 +291,7 @@ __device__ inline void sort_desc_wave(const double* d, int stride, int n, int* o
       const double lj = d[j * stride];
       pos += (lj > li) || (lj == li && j < lane);
     }
-    order[pos] = lane;
+    if (pos < n) order[pos] = lane;
   }
   wave_sync();
 }
