@@ -82,24 +82,143 @@ def project_flops(N, ranks):
     return float((2 * (r1 * N ** 3 + r1 * r2 * N * N + r1 * r2 * r3 * N)).sum())
 
 
-def measured_traffic(workload_name, fam):
-    """HBM bytes per cell of a kernel family from the committed counter
-    summaries (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated, divided by the
-    cells the profiled launches covered), or None when there is none for this
-    workload or the kernel's source has changed since."""
-    import glob
-    import hashlib
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
-        with open(path) as fh:
-            d = json.load(fh)
-        k = d.get("kernels", {}).get(fam)
-        if d.get("workload") != workload_name or not k:
-            continue
-        with open(os.path.join(ROOT, k["source"]), "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest() != k["sha256"]:
-                return None
-        return k["fetch_bytes_per_cell"] + k["write_bytes_per_cell"]
+FAMILIES = {"rround": "k_rround", "moments": "k_moments", "expand": "k_expand", "gram": "k_gram",
+            "eig": "k_eig", "project": "k_project"}
+SOURCES = {"rround": "k_rround.hip", "moments": "k_moments.hip", "expand": "k_expand.hip", "gram": "k_gram.hip",
+           "eig": "k_eig.hip", "project": "k_project.hip"}
+
+
+def family_of(kernel_name):
+    """Kernel family of a demangled kernel name (k_expand_pipe<...> -> expand)."""
+    import re
+    m = re.search(r"\b(k_[a-z0-9_]+)\s*[<(]", kernel_name)
+    base = m.group(1) if m else kernel_name
+    for fam, stem in FAMILIES.items():
+        if base == stem or (base.startswith(stem + "_") and base != "k_expand_plain"):
+            return fam
     return None
+
+
+def source_sha(fam):
+    import hashlib
+    path = os.path.join(ROOT, "paper_1912_04582_amd", "csrc", SOURCES[fam])
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(workload_name, fam):
+    """HBM bytes per step of a kernel family in the timed window, from the
+    committed counter summary (FETCH_SIZE and WRITE_SIZE runs of the same
+    command, copy-calibrated), or None when there is none for this workload
+    or the kernel's source has changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload_name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    k = d.get("kernels", {}).get(fam)
+    if not k or k.get("sha256") != source_sha(fam):
+        return None
+    return k["fetch_bytes_per_step"] + k["write_bytes_per_step"]
+
+
+def window_rows(rows, window):
+    """Dispatches of the timed window: from the start of the `window`-th last
+    factor-space (or, without it, moments) launch on; rows sorted by start."""
+    rows = sorted(rows, key=lambda r: r["start"])
+    marks = [r for r in rows if family_of(r["name"]) == "rround"] or \
+        [r for r in rows if family_of(r["name"]) == "moments"]
+    t0 = marks[-window]["start"] if len(marks) >= window else rows[0]["start"]
+    return [r for r in rows if r["start"] >= t0]
+
+
+def trace_summary(trace_csv, window, bench_json=None):
+    """Markdown table of kernel-family times in the timed window of a
+    rocprofv3 --kernel-trace CSV, beside the HIP-event averages of the bench
+    line when given."""
+    import csv
+    rows = []
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            rows.append({"name": r["Kernel_Name"], "start": int(r["Start_Timestamp"]),
+                         "end": int(r["End_Timestamp"])})
+    win = window_rows(rows, window)
+    fam = {}
+    for r in win:
+        f = family_of(r["name"])
+        if f:
+            t = fam.setdefault(f, [0.0, 0])
+            t[0] += (r["end"] - r["start"]) / 1e6
+            t[1] += 1
+    hip = {}
+    if bench_json:
+        with open(bench_json) as fh:
+            b = json.loads(fh.read().strip().splitlines()[-1])
+        for f, ms in b.get("kernel_ms_per_step", {}).items():
+            hip[f] = ms
+    out = ["| family | launches | total (ms) | per step (ms) | average per launch (ms) | HIP events, per step (ms) |",
+           "|---|---|---|---|---|---|"]
+    for f, (ms, n) in sorted(fam.items(), key=lambda kv: -kv[1][0]):
+        he = f"{hip[f]:.3f}" if f in hip else "-"
+        out.append(f"| {f} | {n} | {ms:.2f} | {ms / window:.3f} | {ms / n:.4f} | {he} |")
+    span = (win[-1]["end"] - win[0]["start"]) / 1e6
+    out.append("")
+    out.append(f"Window: the last {window} steps, {len(win)} launches over {span:.1f} ms "
+               f"({span / window:.2f} ms per step of device time span).")
+    return "\n".join(out)
+
+
+def counter_rows(csv_path, counter):
+    import csv
+    rows = []
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            rows.append({"name": r["Kernel_Name"], "id": int(r["Dispatch_Id"]), "value": float(r["Counter_Value"])})
+    # one value per dispatch (the counter summed over its instances)
+    agg = {}
+    for r in rows:
+        a = agg.setdefault(r["id"], {"name": r["name"], "id": r["id"], "value": 0.0})
+        a["value"] += r["value"]
+    return sorted(agg.values(), key=lambda r: r["id"])
+
+
+def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, window, workload_name):
+    """Bytes per step of each kernel family in the timed window (the sum over
+    its launches there, divided by the window's steps: independent of how the
+    step splits its cells into launches): FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) scaled so that the 1 GiB elementwise copy reads and writes
+    1 GiB."""
+    def calib(path, counter):
+        rows = [r for r in counter_rows(path, counter) if "elementwise" in r["name"] or "mul" in r["name"]]
+        v = sorted(r["value"] for r in rows)[len(rows) // 2]  # median of the copy launches
+        return (1 << 30) / (v * 1024.0)
+    fr, fw = calib(copy_fetch_csv, "FETCH_SIZE"), calib(copy_write_csv, "WRITE_SIZE")
+    out = {"workload": workload_name, "window_steps": window,
+           "note": f"HBM bytes per step in the timed window: FETCH_SIZE x {fr:.3f} + WRITE_SIZE x {fw:.3f} "
+                   "(KiB per dispatch, scaled so the 1 GiB copy kernel reads and writes 1 GiB); valid while "
+                   "the kernel source is unchanged",
+           "fetch_scale": fr, "write_scale": fw, "kernels": {}}
+    for counter, scale, key in (("FETCH_SIZE", fr, "fetch_bytes_per_step"), ("WRITE_SIZE", fw, "write_bytes_per_step")):
+        rows = counter_rows(fetch_csv if counter == "FETCH_SIZE" else write_csv, counter)
+        marks = [r for r in rows if family_of(r["name"]) == "rround"] or \
+            [r for r in rows if family_of(r["name"]) == "moments"]
+        i0 = marks[-window]["id"] if len(marks) >= window else rows[0]["id"]
+        fam = {}
+        for r in rows:
+            f = family_of(r["name"])
+            if f and r["id"] >= i0:
+                t = fam.setdefault(f, [0.0, 0, set()])
+                t[0] += r["value"] * 1024.0 * scale
+                t[1] += 1
+                t[2].add(r["name"].replace("void tk::(anonymous namespace)::", "").split("(")[0])
+        for f, (b, n, names) in fam.items():
+            k = out["kernels"].setdefault(f, {"kernels": sorted(names),
+                                              "source": f"paper_1912_04582_amd/csrc/{SOURCES[f]}",
+                                              "sha256": source_sha(f), "launches": n})
+            k[key] = b / window
+    return out
 
 
 def roofline(fam, cfg, mesh, res, steps):
@@ -133,9 +252,8 @@ def roofline(fam, cfg, mesh, res, steps):
     else:
         return None
     achieved = work / launches_per_step / per_launch_s / 1e12
-    per_cell = measured_traffic(cfg["name"], fam)
-    cells_per_step = rp.get("factor", 0) / steps if fam == "rround" else nb
-    traffic = per_cell * cells_per_step / launches_per_step if per_cell is not None else None
+    per_step = measured_traffic(cfg["name"], fam)
+    traffic = per_step / launches_per_step if per_step is not None else None
     return {"bound": bound, "achieved": achieved, "peak": peak / 1e12, "unit": unit,
             "frac": achieved / (peak / 1e12), "traffic": traffic, "kernel": fam,
             "avg_launch_ms": per_launch_s * 1e3, "launches_per_step": launches_per_step,
@@ -452,12 +570,28 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB read + 1 GiB write elementwise copy, five times (the "
                          "reference kernel for scaling HBM byte counters)")
+    ap.add_argument("--trace-summary", nargs="+", metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
+                    help="print the timed window's kernel-family times of a rocprofv3 kernel trace of this "
+                         "script (and the bench line's HIP-event times) as markdown, then exit")
+    ap.add_argument("--traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write profiles/traffic_<workload>.json from FETCH_SIZE / WRITE_SIZE counter runs of "
+                         "this script and of --calibrate-copy, then exit")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--targets", default="", help=argparse.SUPPRESS)
     ap.add_argument("--leg-steps", type=int, default=2, help=argparse.SUPPRESS)
     a = ap.parse_args()
     if a.cpu_leg:
         cpu_leg(a.workload, [int(x) for x in a.targets.split(",")], a.leg_steps)
+        return
+    if a.trace_summary:
+        print(trace_summary(a.trace_summary[0], a.steps or 20, a.trace_summary[1] if len(a.trace_summary) > 1 else None))
+        return
+    if a.traffic:
+        name = synth.make_config(a.workload)["name"]
+        out = traffic_summary(*a.traffic, a.steps or 20, name)
+        with open(os.path.join(ROOT, "profiles", f"traffic_{name}.json"), "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(json.dumps(out, indent=1))
         return
     if a.calibrate_copy:
         import torch
