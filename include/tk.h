@@ -208,9 +208,10 @@ tk_status tk_state_use_graph(tk_state* st, int32_t on);
  * and stream exist.  Results are the same either way.                    */
 tk_status tk_state_streams(tk_state* st, int32_t two, int32_t* available);
 /* Rounding path (Op4, Section "Tensor decompositions").  With
- * factor_space = 1 (the default where available: every face on a
- * coordinate axis and N <= 32) a cell whose own state and far sides all
- * have rank 1 is rounded in the space of its concatenated factors:
+ * factor_space = 1 (the default where available: Tucker states with
+ * N <= 32) a cell whose faces all lie on coordinate-axis planes and whose
+ * own state and far sides all have rank 1 is rounded in the space of its
+ * concatenated factors:
  * Gram-Schmidt QR of the factors, the small core multiplied by the R
  * factors, eigen-decompositions of that core's unfolding Grams, fused with
  * the term assembly; the other cells are rounded in the N-basis (the update
@@ -221,7 +222,8 @@ tk_status tk_state_streams(tk_state* st, int32_t two, int32_t* available);
  * truncation threshold by the rank chosen).  TK_EINVAL when enabling it on
  * a state without the factor-space path.  counts (nullable, [4]) receives
  * and resets: cells rounded in factor space, cells rounded in the N-basis
- * by eager steps, Jacobi sweeps in factor space, and the FP64 operations
+ * by eager steps (not counted for served states), Jacobi sweeps in factor
+ * space, and the FP64 operations
  * of the factor-space rounding (2 per multiply-add of its Gram-Schmidt,
  * core, Gram, rotation, Jacobi and output products).  Waits for the
  * context stream.                                                         */
@@ -333,13 +335,31 @@ typedef struct {
   double* macro_out;     /* caller buffer [n_cells][8], filled when done, may be NULL */
 } tk_result;
 
-/* Continuous batching over one device: admitted requests share the step
- * launches of their N-bucket, states stay resident; admission by memory
- * against hbm_budget.                                                     */
+/* Continuous batching of independent solves over one device.  A worker
+ * thread admits queued requests in arrival order among those whose
+ * estimated device memory fits what the running ones leave of hbm_budget
+ * (0: the context's budget).  The requests admitted together that share N,
+ * precision and whether their mesh has faces off the coordinate axes form
+ * a cohort: the instances of one resident batched state
+ * with its own stream, so one step of the cohort is one set of launches
+ * over all their cells.  Each cohort keeps one step in flight and starts
+ * its next as soon as that one completes, without waiting for the other
+ * cohorts.  A request retires when its residual (tk_state_step) falls
+ * below residual_tol, at max_steps, or with TK_ENUMERIC when one of its
+ * cells turns non-positive or non-finite; its cells are then no longer
+ * stepped, and the cohort's memory returns to the budget when its last
+ * request retires (requests never join a running cohort).  A request's
+ * result does not depend on the requests served beside it.               */
 tk_status tk_serve_create(tk_ctx* ctx, size_t hbm_budget, tk_server** out);
 /* Never blocks; TK_ENOMEM only for a request that could never fit.       */
 tk_status tk_serve_submit(tk_server* srv, const tk_request* req, uint64_t* ticket);
+/* Returns the request's status (TK_PENDING while queued or running) and
+ * fills *res; TK_ENOTFOUND for an unknown ticket.                         */
 tk_status tk_serve_poll(tk_server* srv, uint64_t ticket, tk_result* res);
+/* out4[0] cohorts formed, [1] cohort steps (shared launch sets), [2]
+ * request steps, [3] requests in the largest cohort.                      */
+tk_status tk_serve_stats(tk_server* srv, int64_t* out4);
+/* Stops the worker (running requests stay TK_PENDING) and frees all.     */
 tk_status tk_serve_destroy(tk_server* srv);
 
 #ifdef __cplusplus

@@ -1159,7 +1159,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand_obl(DevState d, int c0, T* X, 
   T* sd = sxi + N;    // 3 N
   __shared__ double s_nrm[kSlots][3];
   __shared__ ObTab s_tab;
-  const int c = c0 + blockIdx.x;
+  if (d.cells && c0 + (int)blockIdx.x >= *d.cells_n) return;
+  const int c = d.cells ? d.cells[c0 + blockIdx.x] : c0 + blockIdx.x;
   ob_tables<N, BLOCK, T>(d, c, sxi, sd, s_nrm);
   if (threadIdx.x == 0) ob_table(d, c, N, s_tab);
   __syncthreads();
@@ -1178,7 +1179,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand_obl_general(DevState d, int c0
   const int n = *list_n;
   for (int b = blockIdx.x; b < n; b += gridDim.x) {
     const int bi = list[b];
-    ob_slow<N, BLOCK, T>(d, c0 + bi, X + (size_t)bi * N * N * N, smem);
+    ob_slow<N, BLOCK, T>(d, d.cells ? d.cells[c0 + bi] : c0 + bi, X + (size_t)bi * N * N * N, smem);
     __syncthreads();
   }
 }

@@ -86,6 +86,7 @@ __global__ __launch_bounds__(kMomThreads, 4) void k_moments(DevState d) {
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
   const InstParams P = d.ip[d.inst[c]];
+  if (P.frozen) return;  // macroparameters kept as they were
   const int r1 = d.rank[3 * c], r2 = d.rank[3 * c + 1], r3 = d.rank[3 * c + 2];
   const int rr[3] = {r1, r2, r3};
   for (int o = tid; o < N; o += kMomThreads) sxi[o] = P.xi_min + o * P.dxi;
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(kMomThreads, 4) void k_moments(DevState d) {
     const bool ok = (n > 0.0) && (T > 0.0) && isfinite(n) && isfinite(T) && isfinite(u[0]) &&
                     isfinite(u[1]) && isfinite(u[2]) && isfinite(q[0]) && isfinite(q[1]) &&
                     isfinite(q[2]);
-    if (!ok) atomicOr(d.flag, 1);
+    if (!ok) atomicOr(&d.flag[d.inst[c]], 1);
   }
   // wall ghost densities
   for (int l = 0; l < kSlots; ++l) {

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kPM) void k_plain_moments(DevPlain d) {
   M[0] = n; M[1] = u[0]; M[2] = u[1]; M[3] = u[2]; M[4] = T0;
   M[5] = q[0]; M[6] = q[1]; M[7] = q[2];
   d.nu[c] = nu;
-  if (!(n > 0.0) || !(T0 > 0.0) || !isfinite(n) || !isfinite(T0)) atomicOr(d.flag, 1);
+  if (!(n > 0.0) || !(T0 > 0.0) || !isfinite(n) || !isfinite(T0)) atomicOr(&d.flag[d.inst[c]], 1);
   for (int s = 0; s < kSlots; ++s) {
     if (d.slot_kind[kSlots * c + s] != SK_WALL) continue;
     const int a = d.slot_axis[kSlots * c + s];

@@ -564,6 +564,7 @@ __global__ __launch_bounds__(kRThreads, 3) void k_rround(DevState d, const int* 
   const int n = list ? *list_n : d.n_cells;
   for (int b = blockIdx.x; b < n; b += gridDim.x) {
     const int c = list ? list[b] : b;
+    if (d.ip[d.inst[c]].frozen) continue;  // neither rounded nor listed
     double fl = 0.0;
     const bool done = rround_cell<N, RM, GM, QM, SC>(d, c, smem, stats ? stats + 2 : nullptr, &fl);
     if (threadIdx.x == 0) {

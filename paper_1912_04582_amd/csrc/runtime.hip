@@ -65,6 +65,13 @@ tk_status ctx_fail(tk_ctx* ctx, tk_status st, const std::string& msg) {
   return st;
 }
 
+int face_axis(const double* e) {
+  int axis = -1, nz = 0;
+  for (int a = 0; a < 3; ++a)
+    if (e[a] != 0.0) { axis = a; ++nz; }
+  return (nz == 1 && std::fabs(std::fabs(e[axis]) - 1.0) <= 1e-12) ? axis : -1;
+}
+
 tk_status ctx_hip(tk_ctx* ctx, hipError_t e, const char* what) {
   if (e == hipSuccess) return TK_OK;
   return ctx_fail(ctx, e == hipErrorOutOfMemory ? TK_ENOMEM : TK_EDEVICE,
@@ -181,10 +188,8 @@ static tk_status mesh_build(tk_ctx* ctx, const tk_mesh_desc* d, tk_mesh* m) {
   std::vector<double> close((size_t)nc * 3, 0.0), asum(nc, 0.0);
   auto add_slot = [&](int c, int nb, int8_t kind, const double* e, double sgn, double A) -> tk_status {
     if (cnt[c] >= kSlots) return ctx_fail(ctx, TK_EINVAL, "mesh: cell " + std::to_string(c) + " has more than 6 faces");
-    int axis = -1, nz = 0;
-    for (int a = 0; a < 3; ++a)
-      if (e[a] != 0.0) { axis = a; ++nz; }
-    const bool on_axis = (nz == 1 && std::fabs(std::fabs(e[axis]) - 1.0) <= 1e-12);
+    int axis = face_axis(e);
+    const bool on_axis = axis >= 0;
     if (!on_axis) {
       axis = -1;
       if (kind == SK_SYM || kind == SK_WALL)
@@ -365,7 +370,7 @@ size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk) {
 }
 
 static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* meshes, const tk_params* params,
-                              const double* const* macros, bool plain, tk_state** out) {
+                              const double* const* macros, bool plain, tk_state** out, bool served = false) {
   if (!ctx || !out || count <= 0 || !meshes || !params || !macros) return ctx_fail(ctx, TK_EINVAL, "state: null argument");
   *out = nullptr;
   if (ctx->device < 0) return ctx_fail(ctx, TK_EDEVICE, "state: host-only context");
@@ -435,7 +440,7 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     P.Kn = p.Kn;
     P.tol = p.tol;
     P.cap = p.rank_cap;
-    P.pad = 0;
+    P.frozen = 0;
     std::vector<int> face_est(m->oblique ? m->n_faces : 0, -1);
     for (int c = 0; c < m->n_cells; ++c) {
       const int g = c0 + c;
@@ -516,11 +521,12 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
   ALLOC(d_macro_prev, double, (size_t)nc * 8);
   ALLOC(d_nu, double, nc);
   ALLOC(d_nw, double, (size_t)nc * kSlots);
-  ALLOC(d_flag, int, 1);
+  ALLOC(d_flag, int, count);
   ALLOC(d_resid, double, count);
   ALLOC(d_macro5, double, (size_t)nc * 5);
   const int n_est = (int)est_inst.size();
   S->oblique = oblique;
+  S->served = served;
   S->n_est = n_est;
   if (oblique) {
     ALLOC(d_slot_nrm, double, (size_t)nc * kSlots * 3);
@@ -551,7 +557,9 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     ALLOC(Wkeep, double, (size_t)nc * 3 * N * N);
     ALLOC(d_wvalid, int, (size_t)nc * 3);
     ALLOC(d_rstats, unsigned long long, 8);
-    S->rspace_ok = !oblique && N <= 32;
+    // the factor-space kernel takes or leaves each cell by itself (a cell
+    // with an oblique face goes to the N-basis passes)
+    S->rspace_ok = N <= 32;
     S->rspace = S->rspace_ok;
     if (S->rspace_ok) {
       ALLOC(d_rlistD, int, nc);
@@ -567,7 +575,7 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     // (with a margin), so that no error is recorded when it does not
     const size_t ch = (size_t)S->chunk;
     const size_t need = ch * N * N * N * tsz + ch * 3 * N * N * 8 * (S->mixed ? 1 : 2) + ch * 4 + 4096;
-    if (nc > 1 && ctx->used + need + (64u << 20) <= ctx->budget) {
+    if (nc > 1 && !served && ctx->used + need + (64u << 20) <= ctx->budget) {
       tk_status s2 = TK_OK;
       S->X2 = st_alloc(S, ch * N * N * N * tsz, &s2);
       if (S->X2) S->G2 = (double*)st_alloc(S, ch * 3 * N * N * 8, &s2);
@@ -606,7 +614,7 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     up(S->d_slot_nrm, slot_nrm.data(), sizeof(double) * slot_nrm.size());
     up(S->d_slot_est, slot_est.data(), sizeof(int) * slot_est.size());
   }
-  if (e == hipSuccess) e = hipMemsetAsync(S->d_flag, 0, sizeof(int), q);
+  if (e == hipSuccess) e = hipMemsetAsync(S->d_flag, 0, sizeof(int) * count, q);
   if (e == hipSuccess) e = hipMemsetAsync(S->d_nw, 0, sizeof(double) * (size_t)nc * kSlots, q);
   if (e == hipSuccess) e = hipMemsetAsync(S->d_macro, 0, sizeof(double) * (size_t)nc * 8, q);
   if (e != hipSuccess) { state_free(S); return ctx_hip(ctx, e, "state upload"); }
@@ -753,7 +761,8 @@ static tk_status state_step_once(tk_state* st) {
   // rounding in the space of the concatenated factors: the cells it leaves
   // (their concatenated ranks or core too large for its layouts) are listed
   // for the N-basis passes below; an eager step reads their count back, a
-  // captured step runs passes over every cell that end at the list's count
+  // captured or served step runs passes over every cell that end at the
+  // list's count
   int dense_n = st->nc;
   if (st->rspace) {
     prof_begin(ctx, KID_RROUND, &ev);
@@ -762,7 +771,7 @@ static tk_status state_step_once(tk_state* st) {
     if (e != hipSuccess) return ctx_hip(ctx, e, "rounding in factor space");
     d.cells = st->d_rlistD;
     d.cells_n = st->d_rcnt;
-    if (!st->capturing) {
+    if (!st->capturing && !st->served) {
       e = hipMemcpyAsync(st->h_rcnt, st->d_rcnt, sizeof(int), hipMemcpyDeviceToHost, q);
       if (e == hipSuccess) e = hipStreamSynchronize(q);
       if (e != hipSuccess) return ctx_hip(ctx, e, "rounding list count");
@@ -945,17 +954,40 @@ tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait) {
       e = hipMemcpyAsync(residual, st->d_resid, sizeof(double) * st->ninst, hipMemcpyDeviceToHost, q);
     if (e != hipSuccess) return ctx_hip(ctx, e, "residual");
   }
-  int flag = 0;
-  hipError_t e = hipMemcpyAsync(&flag, st->d_flag, sizeof(int), hipMemcpyDeviceToHost, q);
+  std::vector<int> flag(st->ninst, 0);
+  hipError_t e = hipMemcpyAsync(flag.data(), st->d_flag, sizeof(int) * st->ninst, hipMemcpyDeviceToHost, q);
   if (e == hipSuccess) e = hipStreamSynchronize(q);
   if (e != hipSuccess) return ctx_hip(ctx, e, "step sync");
   prof_harvest(ctx);
-  if (flag) return ctx_fail(ctx, TK_ENUMERIC, "a cell has non-positive or non-finite n or T");
+  for (int k = 0; k < st->ninst; ++k)
+    if (flag[k] && !st->ip_host[k].frozen)
+      return ctx_fail(ctx, TK_ENUMERIC, "a cell of instance " + std::to_string(k) + " has non-positive or non-finite n or T");
   return TK_OK;
 }
 
-// One step with the residual and the numeric flag copied asynchronously to
-// host memory (h_res[n_instances], h_flag); the caller synchronises the stream.
+// One step with the residuals and the numeric flags copied asynchronously to
+// host memory (h_res[n_instances], h_flag[n_instances]); the caller
+// synchronises the stream.
+tk_status state_create_served(tk_ctx* ctx, int count, const tk_mesh* const* meshes, const tk_params* params,
+                              const double* const* macros, tk_state** out) {
+  if (!ctx) return TK_EINVAL;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  return state_create(ctx, count, meshes, params, macros, false, out, true);
+}
+
+// Stops stepping instance k of a state from the next step on (enqueued on
+// the context stream): moments and factor-space rounding skip its cells, so
+// its macroparameters stay as they were.  The N-basis passes reach only the
+// cells that factor-space rounding lists, so on states with that rounding no
+// kernel reads or writes the instance's Tucker data any more.
+tk_status state_freeze_instance(tk_state* st, int k) {
+  if (!st || k < 0 || k >= st->ninst) return TK_EINVAL;
+  st->ip_host[k].frozen = 1;
+  const hipError_t e = hipMemcpyAsync(st->d_ip + k, &st->ip_host[k], sizeof(InstParams), hipMemcpyHostToDevice,
+                                      st->ctx->stream);
+  return ctx_hip(st->ctx, e, "freeze instance");
+}
+
 tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag) {
   tk_ctx* ctx = st->ctx;
   hipStream_t q = ctx->stream;
@@ -968,7 +1000,7 @@ tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag) {
   if ((s = state_moments_now(st)) != TK_OK) return s;
   e = launch_residual(st->d_macro_prev, st->d_macro, st->d_vol, st->d_inst_off, st->ninst, st->d_resid, q);
   if (e == hipSuccess) e = hipMemcpyAsync(h_res, st->d_resid, sizeof(double) * st->ninst, hipMemcpyDeviceToHost, q);
-  if (e == hipSuccess) e = hipMemcpyAsync(h_flag, st->d_flag, sizeof(int), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_flag, st->d_flag, sizeof(int) * st->ninst, hipMemcpyDeviceToHost, q);
   return ctx_hip(ctx, e, "residual");
 }
 
@@ -1333,7 +1365,7 @@ tk_status tk_state_rounding(tk_state* st, int32_t factor_space, int64_t* counts)
   tk_ctx* ctx = st->ctx;
   std::lock_guard<std::recursive_mutex> g(ctx->mu);
   if (factor_space > 0 && !st->rspace_ok)
-    return ctx_fail(ctx, TK_EINVAL, "rounding in factor space needs axis-aligned faces, N <= 32 and a Tucker state");
+    return ctx_fail(ctx, TK_EINVAL, "rounding in factor space needs N <= 32 and a Tucker state");
   if (factor_space >= 0) {
     st->rspace = factor_space > 0;
     // the graphs captured for the other path

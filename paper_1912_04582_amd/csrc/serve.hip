@@ -1,17 +1,27 @@
 // Serving: continuous batching of independent solves on one device.
 //
-// Each admitted request gets its own sub-context (own default-priority HIP
-// stream), mesh and Tucker state, so requests never share numerical work
-// and a result is the same alone or in a mix.  A worker thread
-//   1. admits queued requests, in arrival order, whenever the estimated
-//      device memory of the request fits what the running ones leave of
-//      the budget (a request that could never fit is refused at submit);
-//   2. enqueues one step, with its residual, for every running request on
-//      that request's stream, so their kernels overlap on the device;
-//   3. waits for the streams, retires the requests whose residual fell below
-//      their tolerance or that reached their step limit (macroparameters
-//      copied out), and frees their memory for the next admissions.
+// Requests admitted together that share N, precision and whether their
+// mesh has faces off the coordinate axes (which selects the expansion
+// kernels) become the instances of one batched state (a cohort), so a step
+// of a cohort is one set of launches over the cells of all its requests.  A worker thread
+//   1. admits queued requests, in arrival order among those that fit,
+//      whenever their estimated device memory fits what the running cohorts
+//      leave of the budget (a request that could never fit is refused at
+//      submit), and forms cohorts of them, each with its own sub-context,
+//      default-priority stream and state;
+//   2. keeps one step in flight per cohort, with the residual and the numeric
+//      flag of every instance copied back; a cohort whose step has completed
+//      gets its next step at once, without waiting for the other cohorts;
+//   3. retires a request whose residual fell below its tolerance, that
+//      reached its step limit, or whose cells turned non-finite: its
+//      macroparameters are copied out and its instance is frozen (moments
+//      and rounding skip its cells from the next step on).  A cohort's
+//      memory returns to the budget when its last request retires.
+// Instances never exchange data and every kernel's arithmetic on a cell is
+// the same whichever cells share its launch, so a request's result does not
+// depend on the requests served beside it.
 // Times are seconds since the server was created.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -34,16 +44,28 @@ struct ServeReq {
   int32_t max_steps = 0;
   double res_tol = 0.0;
   size_t bytes = 0;
+  bool oblique = false;  // a face off the coordinate axes
   double t_arrive = 0, t_admit = -1, t_done = -1;
   tk_status status = TK_PENDING;
   int32_t steps = 0;
   double residual = INFINITY;
   std::vector<double> macro_out;
+};
+
+// Requests stepped by one batched state; owned by the worker thread.
+struct Cohort {
   tk_ctx* ctx = nullptr;
-  tk_mesh* mesh = nullptr;
+  std::vector<tk_mesh*> meshes;
   tk_state* st = nullptr;
-  double* h_res = nullptr;
-  int* h_flag = nullptr;
+  std::vector<ServeReq*> mem;  // instance k = mem[k]
+  std::vector<char> live;
+  int n_live = 0;
+  double* h_res = nullptr;     // pinned [instances]
+  int* h_flag = nullptr;       // pinned [instances]
+  hipEvent_t ev = nullptr;     // end of the step in flight
+  bool inflight = false;
+  tk_status step_status = TK_OK;
+  size_t bytes = 0;
 };
 
 }  // namespace
@@ -59,7 +81,8 @@ struct tk_server {
   uint64_t next = 1;
   std::map<uint64_t, std::unique_ptr<ServeReq>> reqs;
   std::deque<uint64_t> queue;
-  std::vector<ServeReq*> running;
+  std::vector<std::unique_ptr<Cohort>> cohorts;  // worker thread only
+  int64_t stats[4] = {0, 0, 0, 0};  // cohorts, cohort steps, request steps, largest cohort
   std::chrono::steady_clock::time_point t0;
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -68,37 +91,114 @@ struct tk_server {
 
 namespace {
 
-void release(ServeReq* r) {
-  if (r->st) tk_state_destroy(r->st);
-  if (r->mesh) tk_mesh_destroy(r->mesh);
-  if (r->ctx) tk_ctx_destroy(r->ctx);
-  if (r->h_res) (void)hipHostFree(r->h_res);
-  if (r->h_flag) (void)hipHostFree(r->h_flag);
-  r->st = nullptr;
-  r->mesh = nullptr;
-  r->ctx = nullptr;
-  r->h_res = nullptr;
-  r->h_flag = nullptr;
+void release(Cohort* c) {
+  if (c->st) tk_state_destroy(c->st);
+  for (tk_mesh* m : c->meshes) tk_mesh_destroy(m);
+  if (c->ev) (void)hipEventDestroy(c->ev);
+  if (c->ctx) tk_ctx_destroy(c->ctx);
+  if (c->h_res) (void)hipHostFree(c->h_res);
+  if (c->h_flag) (void)hipHostFree(c->h_flag);
+  c->st = nullptr;
+  c->meshes.clear();
+  c->ev = nullptr;
+  c->ctx = nullptr;
+  c->h_res = nullptr;
+  c->h_flag = nullptr;
 }
 
-tk_status admit(tk_server* srv, ServeReq* r) {
-  tk_status s = tk_ctx_create(srv->parent->device, r->bytes + (256u << 20), nullptr, &r->ctx);
-  if (s == TK_OK) s = tk_mesh_load(r->ctx, &r->desc, &r->mesh);
-  if (s == TK_OK) s = tk_state_init(r->ctx, r->mesh, &r->params, r->macro.data(), &r->st);
-  // one rounding pass per step (no pass-size trials: each request runs alone
-  // on its stream and its trial steps would serialise the mix)
-  if (s == TK_OK) s = tk_state_set_chunk(r->st, r->st->chunk_max);
-  if (s == TK_OK && (hipHostMalloc((void**)&r->h_res, sizeof(double)) != hipSuccess ||
-                     hipHostMalloc((void**)&r->h_flag, sizeof(int)) != hipSuccess))
+tk_status form(int device, Cohort* c) {
+  const int n = (int)c->mem.size();
+  for (ServeReq* r : c->mem) c->bytes += r->bytes;
+  tk_status s = tk_ctx_create(device, c->bytes + (256u << 20), nullptr, &c->ctx);
+  std::vector<tk_params> params;
+  std::vector<const double*> macros;
+  for (int k = 0; k < n && s == TK_OK; ++k) {
+    tk_mesh* m = nullptr;
+    s = tk_mesh_load(c->ctx, &c->mem[k]->desc, &m);
+    if (s == TK_OK) c->meshes.push_back(m);
+    params.push_back(c->mem[k]->params);
+    macros.push_back(c->mem[k]->macro.data());
+  }
+  if (s == TK_OK)
+    s = state_create_served(c->ctx, n, (const tk_mesh* const*)c->meshes.data(), params.data(), macros.data(),
+                            &c->st);
+  // one rounding pass per step (pass-size trials would serialise the mix)
+  if (s == TK_OK) s = tk_state_set_chunk(c->st, c->st->chunk_max);
+  if (s == TK_OK && (hipHostMalloc((void**)&c->h_res, sizeof(double) * n) != hipSuccess ||
+                     hipHostMalloc((void**)&c->h_flag, sizeof(int) * n) != hipSuccess ||
+                     hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess))
     s = TK_EDEVICE;
+  c->live.assign(n, 1);
+  c->n_live = n;
   return s;
 }
 
+struct Out {
+  ServeReq* r;
+  tk_status status;
+  bool finished, stepped;
+  double residual;
+  std::vector<double> macro;
+};
+
+// Outcome of a cohort's completed step for each of its running requests;
+// the requests that finish are frozen in the state.
+void collect(Cohort* c, std::vector<Out>& outs) {
+  const size_t first = outs.size();
+  bool copy = false;
+  for (size_t k = 0; k < c->mem.size(); ++k) {
+    if (!c->live[k]) continue;
+    ServeReq* r = c->mem[k];
+    Out o{r, TK_PENDING, false, false, r->residual, {}};
+    if (c->step_status != TK_OK) {
+      o.status = c->step_status;
+      o.finished = true;
+    } else {
+      o.stepped = true;
+      o.residual = c->h_res[k];
+      if (c->h_flag[k]) {
+        o.status = TK_ENUMERIC;
+        o.finished = true;
+      } else if (o.residual < r->res_tol || r->steps + 1 >= r->max_steps) {
+        o.status = TK_OK;
+        o.finished = true;
+        copy = true;
+      }
+    }
+    outs.push_back(std::move(o));
+  }
+  if (copy) {
+    std::vector<double> all((size_t)c->st->nc * 8);
+    const tk_status s = tk_moments(c->st, all.data());
+    for (size_t i = first; i < outs.size(); ++i) {
+      Out& o = outs[i];
+      if (!o.finished || o.status != TK_OK) continue;
+      if (s != TK_OK) {
+        o.status = s;
+        continue;
+      }
+      const size_t k = std::find(c->mem.begin(), c->mem.end(), o.r) - c->mem.begin();
+      const size_t a = (size_t)c->st->inst_off[k], b = (size_t)c->st->inst_off[k + 1];
+      o.macro.assign(all.begin() + 8 * a, all.begin() + 8 * b);
+    }
+  }
+  for (size_t i = first; i < outs.size(); ++i) {
+    if (!outs[i].finished) continue;
+    const size_t k = std::find(c->mem.begin(), c->mem.end(), outs[i].r) - c->mem.begin();
+    c->live[k] = 0;
+    --c->n_live;
+    if (c->n_live > 0 && state_freeze_instance(c->st, (int)k) != TK_OK) c->step_status = TK_EDEVICE;
+  }
+}
+
 void worker_loop(tk_server* srv) {
+  (void)hipSetDevice(srv->parent->device);
   std::unique_lock<std::mutex> lk(srv->mu);
   for (;;) {
     if (srv->stop) break;
-    // 1. admission by memory, in arrival order among those that fit
+    // 1. admission by memory, in arrival order among those that fit; one
+    // cohort per (N, precision, oblique) of the admitted requests
+    std::vector<ServeReq*> adm;
     for (auto it = srv->queue.begin(); it != srv->queue.end();) {
       ServeReq* r = srv->reqs[*it].get();
       if (srv->in_use + r->bytes > srv->budget) {
@@ -108,75 +208,119 @@ void worker_loop(tk_server* srv) {
       it = srv->queue.erase(it);
       srv->in_use += r->bytes;
       r->t_admit = srv->now();
+      adm.push_back(r);
+    }
+    if (!adm.empty()) {
       lk.unlock();
-      const tk_status s = admit(srv, r);
+      std::vector<std::unique_ptr<Cohort>> made, failed;
+      for (ServeReq* r : adm) {
+        Cohort* c = nullptr;
+        for (auto& m : made)
+          if (m->mem[0]->params.N == r->params.N && m->mem[0]->params.precision == r->params.precision &&
+              m->mem[0]->oblique == r->oblique)
+            c = m.get();
+        if (!c) {
+          made.emplace_back(new Cohort());
+          c = made.back().get();
+        }
+        c->mem.push_back(r);
+      }
+      for (auto it = made.begin(); it != made.end();) {
+        const tk_status s = form(srv->parent->device, it->get());
+        if (s == TK_OK) {
+          ++it;
+          continue;
+        }
+        release(it->get());
+        (*it)->step_status = s;
+        failed.push_back(std::move(*it));
+        it = made.erase(it);
+      }
       lk.lock();
-      if (s != TK_OK) {
-        release(r);
-        r->status = s;
-        r->t_done = srv->now();
-        srv->in_use -= r->bytes;
-      } else {
-        srv->running.push_back(r);
+      const double t = srv->now();
+      for (auto& c : failed)
+        for (ServeReq* r : c->mem) {
+          r->status = c->step_status;
+          r->t_done = t;
+          srv->in_use -= r->bytes;
+        }
+      for (auto& c : made) {
+        srv->stats[0] += 1;
+        srv->stats[3] = std::max<int64_t>(srv->stats[3], (int64_t)c->mem.size());
+        srv->cohorts.push_back(std::move(c));
       }
     }
-    if (srv->running.empty()) {
+    if (srv->cohorts.empty()) {
       srv->cv.wait(lk, [&] { return srv->stop || !srv->queue.empty(); });
       continue;
     }
-    std::vector<ServeReq*> run = srv->running;
     lk.unlock();
-    // 2. one step of every running request, overlapped across streams
-    std::vector<tk_status> st(run.size(), TK_OK);
-    for (size_t i = 0; i < run.size(); ++i) {
-      std::lock_guard<std::recursive_mutex> g(run[i]->ctx->mu);
-      st[i] = state_step_residual_async(run[i]->st, run[i]->h_res, run[i]->h_flag);
+    // 2. a step in flight for every cohort
+    for (auto& c : srv->cohorts) {
+      if (c->inflight) continue;
+      c->inflight = true;
+      if (c->step_status != TK_OK) continue;  // retired below with that status
+      std::lock_guard<std::recursive_mutex> g(c->ctx->mu);
+      tk_status s = state_step_residual_async(c->st, c->h_res, c->h_flag);
+      if (s == TK_OK && hipEventRecord(c->ev, c->ctx->stream) != hipSuccess) s = TK_EDEVICE;
+      c->step_status = s;  // an enqueue error retires the cohort's requests below
     }
-    // 3. completion; results are published to pollers under the lock only
-    struct Out {
-      ServeReq* r;
-      tk_status status;
-      bool finished;
-      double residual;
-      std::vector<double> macro;
-    };
-    std::vector<Out> outs;
-    outs.reserve(run.size());
-    for (size_t i = 0; i < run.size(); ++i) {
-      ServeReq* r = run[i];
-      Out o{r, TK_PENDING, false, r->residual, {}};
-      if (st[i] == TK_OK && hipStreamSynchronize(r->ctx->stream) != hipSuccess) st[i] = TK_EDEVICE;
-      if (st[i] != TK_OK) {
-        o.status = st[i];
-        o.finished = true;
-      } else {
-        o.residual = *r->h_res;
-        const int steps = r->steps + 1;
-        if (*r->h_flag) {
-          o.status = TK_ENUMERIC;
-          o.finished = true;
-        } else if (o.residual < r->res_tol || steps >= r->max_steps) {
-          o.macro.resize((size_t)r->desc.n_cells * 8);
-          o.status = tk_moments(r->st, o.macro.data());
-          o.finished = true;
+    // 3. the cohorts whose step has completed (polled: none waits for another)
+    std::vector<Cohort*> ready;
+    for (;;) {
+      for (auto& c : srv->cohorts) {
+        if (c->step_status != TK_OK) {
+          ready.push_back(c.get());
+          continue;
+        }
+        const hipError_t q = hipEventQuery(c->ev);
+        if (q == hipSuccess) {
+          ready.push_back(c.get());
+        } else if (q != hipErrorNotReady) {
+          c->step_status = TK_EDEVICE;
+          ready.push_back(c.get());
         }
       }
-      outs.push_back(std::move(o));
+      if (!ready.empty()) break;
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
+    std::vector<Out> outs;
+    int64_t stepped = 0;
+    for (Cohort* c : ready) {
+      if (c->step_status == TK_OK) stepped += 1;
+      collect(c, outs);
+      c->inflight = false;
+    }
+    // results are published to pollers under the lock only
+    std::vector<std::unique_ptr<Cohort>> done;
     lk.lock();
     const double t = srv->now();
-    for (size_t i = 0; i < outs.size(); ++i) {
-      Out& o = outs[i];
+    srv->stats[1] += stepped;
+    for (Out& o : outs) {
       ServeReq* r = o.r;
-      if (st[i] == TK_OK) r->steps += 1;
+      if (o.stepped) {
+        r->steps += 1;
+        srv->stats[2] += 1;
+      }
       r->residual = o.residual;
       if (!o.finished) continue;
       r->macro_out = std::move(o.macro);
       r->t_done = t;
       r->status = o.status;
-      release(r);
-      srv->in_use -= r->bytes;
-      srv->running.erase(std::find(srv->running.begin(), srv->running.end(), r));
+    }
+    for (auto it = srv->cohorts.begin(); it != srv->cohorts.end();) {
+      if ((*it)->n_live > 0) {
+        ++it;
+        continue;
+      }
+      srv->in_use -= (*it)->bytes;
+      done.push_back(std::move(*it));
+      it = srv->cohorts.erase(it);
+    }
+    if (!done.empty()) {
+      lk.unlock();
+      for (auto& c : done) release(c.get());
+      lk.lock();
     }
   }
 }
@@ -227,6 +371,7 @@ tk_status tk_serve_submit(tk_server* srv, const tk_request* req, uint64_t* ticke
   r->max_steps = req->max_steps;
   r->res_tol = req->residual_tol;
   r->bytes = state_bytes_estimate(nc, req->params, false, nc);
+  for (int f = 0; f < nf && !r->oblique; ++f) r->oblique = face_axis(&r->fn[3 * (size_t)f]) < 0;
   std::lock_guard<std::mutex> g(srv->mu);
   if (srv->stop) return TK_EBUSY;
   if (r->bytes > srv->budget) return TK_ENOMEM;
@@ -256,6 +401,13 @@ tk_status tk_serve_poll(tk_server* srv, uint64_t ticket, tk_result* res) {
   return r->status;
 }
 
+tk_status tk_serve_stats(tk_server* srv, int64_t* out4) {
+  if (!srv || !out4) return TK_EINVAL;
+  std::lock_guard<std::mutex> g(srv->mu);
+  for (int i = 0; i < 4; ++i) out4[i] = srv->stats[i];
+  return TK_OK;
+}
+
 tk_status tk_serve_destroy(tk_server* srv) {
   if (!srv) return TK_EINVAL;
   {
@@ -264,7 +416,7 @@ tk_status tk_serve_destroy(tk_server* srv) {
     srv->cv.notify_all();
   }
   if (srv->worker.joinable()) srv->worker.join();
-  for (auto& kv : srv->reqs) release(kv.second.get());
+  for (auto& c : srv->cohorts) release(c.get());
   delete srv;
   return TK_OK;
 }

@@ -33,7 +33,7 @@ struct InstParams {
   double xi_min, dxi;
   double dt, Rg, m, Pr, omega, Kn, tol;
   int cap;
-  int pad;
+  int frozen;  // 1: the instance is no longer stepped (a retired served request)
 };
 
 // Device views used by the step kernels.  Factor storage: fac[cell][a][k][i]
@@ -63,7 +63,7 @@ struct DevState {
   double* macro;
   double* nu;
   double* nw;      // [nc][6]
-  int* flag;       // numeric error flag
+  int* flag;       // numeric error flag per instance
   // oblique faces (slot_axis < 0): outward normal, estimate index and data
   const double* slot_nrm;  // [nc][6][3]
   const int* slot_est;     // [nc][6]

@@ -128,6 +128,7 @@ struct tk_state {
   // and a pinned word for that count, read back each eager step
   bool rspace = false;
   bool rspace_ok = false;  // the state supports it
+  bool served = false;     // a server's state: no second workspace, eager steps never wait on the host
   int* d_rlistD = nullptr;
   int* d_rcnt = nullptr;
   int* d_wvalid = nullptr;
@@ -144,9 +145,14 @@ struct tk_state {
 // shared helpers (runtime.hip)
 tk_status ctx_fail(tk_ctx* ctx, tk_status st, const std::string& msg);
 tk_status ctx_hip(tk_ctx* ctx, hipError_t e, const char* what);
+// the coordinate axis a unit face normal lies on, or -1 (an oblique face)
+int face_axis(const double* e);
 void* ctx_alloc(tk_ctx* ctx, size_t bytes, tk_status* st);
 void ctx_free(tk_ctx* ctx, void* p);
 tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait);
 size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk);
 void state_tune_begin(tk_state* st);
 tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag);
+tk_status state_create_served(tk_ctx* ctx, int count, const tk_mesh* const* meshes, const tk_params* params,
+                              const double* const* macros, tk_state** out);
+tk_status state_freeze_instance(tk_state* st, int k);

@@ -30,7 +30,7 @@ EXPORTED = [
     "tk_state_ranks", "tk_state_export", "tk_round", "tk_round_tucker", "tk_round_tucker_noalloc",
     "tk_plain_init", "tk_ctx_create_ex",
     "tk_serve_create",
-    "tk_serve_submit", "tk_serve_poll", "tk_serve_destroy",
+    "tk_serve_submit", "tk_serve_poll", "tk_serve_stats", "tk_serve_destroy",
 ]
 
 
@@ -133,6 +133,7 @@ def lib():
             "tk_serve_create": [P, C.c_size_t, C.POINTER(P)],
             "tk_serve_submit": [P, C.POINTER(tk_request), C.POINTER(C.c_uint64)],
             "tk_serve_poll": [P, C.c_uint64, C.POINTER(tk_result)],
+            "tk_serve_stats": [P, C.POINTER(C.c_int64)],
             "tk_serve_destroy": [P],
         }
         for name, args in sig.items():
@@ -415,7 +416,9 @@ class State:
 
 
 class Server:
-    """tk_serve_*: continuous batching of independent solves on one device."""
+    """tk_serve_*: continuous batching of independent solves on one device
+    (requests admitted together with the same N and precision share one
+    batched state and its launches)."""
 
     def __init__(self, ctx, budget=0):
         self.ctx = ctx
@@ -444,6 +447,13 @@ class Server:
         return {"status": res.status, "steps": res.steps, "residual": res.residual,
                 "t_arrive": res.t_arrive, "t_admit": res.t_admit, "t_done": res.t_done,
                 "macros": out if res.status != TK_PENDING else None}
+
+    def stats(self):
+        """Cohorts formed, cohort steps (shared launch sets), request steps,
+        requests in the largest cohort."""
+        v = (C.c_int64 * 4)()
+        _check(lib().tk_serve_stats(self.h, v), self.ctx.h)
+        return {"cohorts": v[0], "cohort_steps": v[1], "request_steps": v[2], "largest_cohort": v[3]}
 
     def close(self):
         if self.h:

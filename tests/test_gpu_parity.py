@@ -304,12 +304,15 @@ def test_jittered_mesh_oblique_faces(ctx, precision, N, cap, tol, steps, bar):
 
 
 def test_serving_alone_equals_mix(ctx):
-    """Served requests: results equal to the same request served alone."""
+    """Served requests: results equal to the same request served alone; the
+    two N = 16 requests on axis-aligned meshes, submitted together, share
+    one batched state (with different rank caps and tolerances)."""
     import time
     reqs = []
     for k, (mk, N, cap, tol) in enumerate([(lambda: synth.periodic_box(3), 16, 4, 1e-5),
                                            (lambda: synth.jittered_box(3, 3, 3, 1 / 3, seed=3), 16, 5, 1e-6),
-                                           (lambda: synth.periodic_box(4, length=0.5), 24, 6, 1e-5)]):
+                                           (lambda: synth.periodic_box(4, length=0.5), 24, 6, 1e-5),
+                                           (lambda: synth.periodic_box(3, length=0.7), 16, 6, 1e-6)]):
         m = mk()
         cfg = dict(N=N, xi_max=4.5, cap=cap, tol=tol, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=0.2, Rg=0.5, m=1.0,
                    seed=40 + k, init="random", precision="mixed")
@@ -328,12 +331,15 @@ def test_serving_alone_equals_mix(ctx):
                 if r["status"] != tk.TK_PENDING:
                     out[t] = r
             time.sleep(0.01)
+        stats = srv.stats()
         srv.close()
-        return [out[t] for t in tickets]
+        return [out[t] for t in tickets], stats
 
-    mix = serve(reqs)
+    mix, stats = serve(reqs)
+    assert stats["largest_cohort"] == 2 and stats["cohorts"] == 3, stats
+    assert stats["request_steps"] == 4 * 12 and stats["cohort_steps"] == 3 * 12, stats
     for k, item in enumerate(reqs):
-        alone = serve([item])[0]
+        alone = serve([item])[0][0]
         assert mix[k]["status"] == tk.TK_OK and alone["status"] == tk.TK_OK
         assert mix[k]["steps"] == alone["steps"] == 12
         assert np.array_equal(mix[k]["macros"], alone["macros"])
