@@ -262,6 +262,25 @@ tk_status tk_step(tk_state* st, int32_t nsteps, double* residual);
 /* Enqueue nsteps steps without waiting (no residual, no numeric check).   */
 tk_status tk_step_async(tk_state* st, int32_t nsteps);
 
+/* iters LU-SGS implicit iterations (Section "Tensorized discrete velocity
+ * method", implicit scheme): eq. linear-system times dt,
+ *   [I - dt dR/df] df = dt R(f),   f <- f + df,
+ * with f_S and the boundary ghosts held fixed in the Jacobian, the far-cell
+ * blocks (dt A / V) P_in of the explicit fluxes, and the diagonal of eq.
+ * diagonal_term with |xi_n| replaced by the bound |xi| of eq.
+ * xin-one-rank-approx, (1 + dt nu) 1 + (dt / (2 V)) (sum_l A_l) |xi|, taken
+ * as its rank-1 truncated HOSVD and divided exactly in rank-1 form (eq.
+ * one_rank_division).  Symmetric Gauss-Seidel order: a greedy colouring of
+ * the face graph (cells in index order, the smallest colour no earlier
+ * neighbour has); the forward sweep forms df* colour by colour ascending,
+ * the backward sweep df descending (cells without a later neighbour keep
+ * df*), each rounded to the state's tolerance and cap, and f + df is
+ * rounded into the new state.  dt is the state's (a CFL above the explicit
+ * step's bound of 1 is the point).  residual as for tk_step.  TK_EINVAL
+ * for mixed-precision, plain or N = 48 states and for meshes with faces
+ * off the coordinate axes.  Blocking.                                    */
+tk_status tk_lusgs(tk_state* st, int32_t iters, double* residual);
+
 /* Rank histogram (hist[0..16], ranks are max over modes) and mean
  * compression ratio C = (r1 r2 r3 + N (r1 + r2 + r3)) / N^3 (Section "Test
  * problem").                                                              */

@@ -113,8 +113,12 @@ __device__ inline void stage_state(const double* core, const double* fac, int CS
   }
 }
 
-template <int N, int BLOCK, typename T>
-__global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
+// LU: the forward LU-SGS stage instead of the explicit update: the cell's
+// own coefficient loses its 1 (dt R instead of f + dt R), the increments
+// df* of the far cells swept earlier are added as further far sides, and the
+// sum is divided by the rank-1 diagonal.
+template <int N, int BLOCK, typename T, bool LU = false>
+__global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X, LuArgs lu) {
   // SPLIT workgroups share a cell, each expanding every source but only its
   // share of the fibres (more, smaller workgroups per CU)
   constexpr int SPLIT = ExpandSplit<N>::S;
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
   expand_fibres<N, BLOCK, T, FIB>(acc, sU, sG, sY, r1, r2, r3, CS, pf);
   __syncthreads();
   {
-    const T cterm = (T)(1.0 - P.dt * nu);
+    const T cterm = (T)((LU ? 0.0 : 1.0) - P.dt * nu);
 #pragma unroll
     for (int f = 0; f < FIB; ++f) {
       const T dd = cterm + sd[N + pf[f] % N] + sd[2 * N + pf[f] / N];
@@ -244,6 +248,33 @@ __global__ __launch_bounds__(BLOCK) void k_expand(DevState d, int c0, T* X) {
     __syncthreads();
     expand_fibres<N, BLOCK, T, FIB>(acc, sU, sG, sY, q1, q2, q3, CS, pf);
     __syncthreads();
+  }
+  if constexpr (LU) {
+    for (int l = 0; l < kSlots; ++l) {
+      if (d.slot_kind[kSlots * c + l] != SK_INTERIOR) continue;
+      const int nb = d.slot_nb[kSlots * c + l];
+      if (lu.col[nb] >= lu.colour) continue;
+      const int ax = d.slot_axis[kSlots * c + l];
+      const double sg = (double)d.slot_sig[kSlots * c + l];
+      const double coef = d.slot_coef[kSlots * c + l];
+      for (int i = tid; i < N; i += BLOCK) sb[i] = (T)(coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0));
+      __syncthreads();
+      const int q1 = lu.rank[3 * nb], q2 = lu.rank[3 * nb + 1], q3 = lu.rank[3 * nb + 2];
+      stage_state<N, BLOCK, T>(lu.core, lu.fac, CS, nb, q1, q2, q3, -1, ax, sb, 1.0, sU, sG);
+      __syncthreads();
+      expand_fibres<N, BLOCK, T, FIB>(acc, sU, sG, sY, q1, q2, q3, CS, pf);
+      __syncthreads();
+    }
+    const double* di = lu.dinv + (size_t)c * (N + 1);
+    for (int i = tid; i < N; i += BLOCK) sb[i] = (T)di[i];
+    __syncthreads();
+    const T isg = (T)di[N];
+#pragma unroll
+    for (int f = 0; f < FIB; ++f) {
+      const T w = sb[pf[f] % N] * sb[pf[f] / N] * isg;
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[f][i] *= sb[i] * w;
+    }
   }
 
   T* out = X + (size_t)cb * N * N * N;
@@ -1298,7 +1329,170 @@ hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, int* l
   auto k = k_expand<N, B, T>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(count * ExpandSplit<N>::S), dim3(B), sh, s, d, c0, (T*)X);
+  hipLaunchKernelGGL(k, dim3(count * ExpandSplit<N>::S), dim3(B), sh, s, d, c0, (T*)X, LuArgs{});
+  return hipGetLastError();
+}
+
+// LU-SGS backward stage and commit of one cell each (FP64, fibre form):
+// backward X = df*_i + D^-1 sum_{upper far cells} b_l o df_m, with b_l the
+// explicit step's far-side row scaling; commit X = f_i + df_i.
+template <int N, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_lu_combine(DevState d, LuArgs lu, int c0, double* X, int stage) {
+  constexpr int FIB = N * N / BLOCK;
+  static_assert(FIB * BLOCK == N * N, "fibres must tile the workgroup");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* smem = reinterpret_cast<double*>(smem_raw);
+  const int CS = d.CS;
+  double* sU = smem;                  // 3 CS N
+  double* sG = sU + 3 * CS * N;       // CS^3
+  double* sY = sG + CS * CS * CS;     // CS CS N
+  double* sb = sY + CS * CS * N;      // N
+  const int cb = blockIdx.x;
+  if (d.cells && c0 + cb >= *d.cells_n) return;
+  const int c = d.cells ? d.cells[c0 + cb] : c0 + cb;
+  const int tid = threadIdx.x;
+  const InstParams P = d.ip[d.inst[c]];
+  int pf[FIB];
+#pragma unroll
+  for (int f = 0; f < FIB; ++f) pf[f] = tid + BLOCK * f;
+  double acc[FIB][N];
+#pragma unroll
+  for (int f = 0; f < FIB; ++f)
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[f][i] = 0.0;
+  if (stage == LU_BACKWARD) {
+    for (int l = 0; l < kSlots; ++l) {
+      if (d.slot_kind[kSlots * c + l] != SK_INTERIOR) continue;
+      const int nb = d.slot_nb[kSlots * c + l];
+      if (lu.col[nb] <= lu.colour) continue;
+      const int ax = d.slot_axis[kSlots * c + l];
+      const double sg = (double)d.slot_sig[kSlots * c + l];
+      const double coef = d.slot_coef[kSlots * c + l];
+      for (int i = tid; i < N; i += BLOCK) sb[i] = coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0);
+      __syncthreads();
+      const int q1 = lu.rank[3 * nb], q2 = lu.rank[3 * nb + 1], q3 = lu.rank[3 * nb + 2];
+      stage_state<N, BLOCK, double>(lu.core, lu.fac, CS, nb, q1, q2, q3, -1, ax, sb, 1.0, sU, sG);
+      __syncthreads();
+      expand_fibres<N, BLOCK, double, FIB>(acc, sU, sG, sY, q1, q2, q3, CS, pf);
+      __syncthreads();
+    }
+    const double* di = lu.dinv + (size_t)c * (N + 1);
+    for (int i = tid; i < N; i += BLOCK) sb[i] = di[i];
+    __syncthreads();
+    const double isg = di[N];
+#pragma unroll
+    for (int f = 0; f < FIB; ++f) {
+      const double w = sb[pf[f] % N] * sb[pf[f] / N] * isg;
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[f][i] *= sb[i] * w;
+    }
+  } else {
+    const int r1 = d.rank[3 * c], r2 = d.rank[3 * c + 1], r3 = d.rank[3 * c + 2];
+    stage_state<N, BLOCK, double>(d.core, d.fac, CS, c, r1, r2, r3, -1, -1, nullptr, 1.0, sU, sG);
+    __syncthreads();
+    expand_fibres<N, BLOCK, double, FIB>(acc, sU, sG, sY, r1, r2, r3, CS, pf);
+    __syncthreads();
+  }
+  // the cell's own increment (df* in the backward stage, df in the commit)
+  const int q1 = lu.rank[3 * c], q2 = lu.rank[3 * c + 1], q3 = lu.rank[3 * c + 2];
+  stage_state<N, BLOCK, double>(lu.core, lu.fac, CS, c, q1, q2, q3, -1, -1, nullptr, 1.0, sU, sG);
+  __syncthreads();
+  expand_fibres<N, BLOCK, double, FIB>(acc, sU, sG, sY, q1, q2, q3, CS, pf);
+  double* out = X + (size_t)cb * N * N * N;
+#pragma unroll
+  for (int f = 0; f < FIB; ++f)
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[(size_t)pf[f] * N + i] = acc[f][i];
+}
+
+// The rank-1 truncated HOSVD of D = a 1 + b |xi| (a = 1 + dt nu, b = (dt /
+// (2 V)) sum_l A_l): by the symmetry of |xi| in the three velocity axes the
+// three factors are one vector u, the leading eigenvector of the mode-1
+// Gram a^2 N^2 1 1^T + a b (1 p^T + p 1^T) + b^2 Q, found by power
+// iteration from the positive start (the Gram is positive, so u is); the
+// core is D x u x u x u = a (sum u)^3 + b sum |xi|(i,j,k) u_i u_j u_k.  One
+// wavefront per cell.
+__device__ inline double lu_wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+template <int N>
+__global__ __launch_bounds__(64) void k_lu_diag(DevState d, const double* pq, double* dinv) {
+  __shared__ double sp[N], sQ[N * N], su[N];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int k = d.inst[c];
+  const InstParams P = d.ip[k];
+  const double* pk = pq + (size_t)k * (N + N * N);
+  for (int o = lane; o < N + N * N; o += 64) {
+    if (o < N) sp[o] = pk[o];
+    else sQ[o - N] = pk[o];
+  }
+  double b = 0.0;
+  if (lane < kSlots && d.slot_kind[kSlots * c + lane] != SK_NONE) b = 0.5 * d.slot_coef[kSlots * c + lane];
+  b = lu_wave_sum(b);
+  const double a = 1.0 + P.dt * d.nu[c];
+  const double t = b / a;
+  double u = lane < N ? 1.0 / sqrt((double)N) : 0.0;
+  wave_sync();
+  for (int it = 0; it < 200; ++it) {
+    if (lane < N) su[lane] = u;
+    wave_sync();
+    const double s1 = lu_wave_sum(u);
+    const double pu = lu_wave_sum(lane < N ? sp[lane] * u : 0.0);
+    double v = 0.0;
+    if (lane < N) {
+      double qu = 0.0;
+      for (int j = 0; j < N; ++j) qu += sQ[lane * N + j] * su[j];
+      v = (double)(N * N) * s1 + t * (pu + s1 * sp[lane]) + t * t * qu;
+    }
+    v /= sqrt(lu_wave_sum(v * v));
+    const double moved = lu_wave_sum(fabs(v - u) > 1e-16 ? 1.0 : 0.0);
+    wave_sync();
+    u = v;
+    if (moved == 0.0) break;
+  }
+  if (lane < N) su[lane] = u;
+  wave_sync();
+  double acc = 0.0;
+  for (int o = lane; o < N * N; o += 64) {
+    const int i = o / N, j = o % N;
+    const double xi = P.xi_min + i * P.dxi, xj = P.xi_min + j * P.dxi;
+    double sk = 0.0;
+    for (int q = 0; q < N; ++q) {
+      const double xk = P.xi_min + q * P.dxi;
+      sk += sqrt(xi * xi + xj * xj + xk * xk) * su[q];
+    }
+    acc += su[i] * su[j] * sk;
+  }
+  const double s3 = lu_wave_sum(acc);
+  const double s1 = lu_wave_sum(u);
+  const double sigma = a * s1 * s1 * s1 + b * s3;
+  double* out = dinv + (size_t)c * (N + 1);
+  if (lane < N) out[lane] = 1.0 / u;
+  if (lane == 0) out[N] = 1.0 / sigma;
+}
+
+template <int N>
+hipError_t launch_lu_t(const DevState& d, const LuArgs& lu, int stage, int c0, int count, double* X,
+                       hipStream_t s) {
+  constexpr int B = ExpandShape<N>::B;
+  const int CS = d.CS;
+  if (stage == LU_FORWARD) {
+    const size_t sh = sizeof(double) * (N + 3 * N + N + 3 * CS * N + CS * CS * CS + CS * CS * N + 3 * CS * N + 64);
+    auto k = k_expand<N, B, double, true>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(count * ExpandSplit<N>::S), dim3(B), sh, s, d, c0, X, lu);
+    return hipGetLastError();
+  }
+  const size_t sh = sizeof(double) * (3 * CS * N + CS * CS * CS + CS * CS * N + N);
+  auto k = k_lu_combine<N, B>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(count), dim3(B), sh, s, d, lu, c0, X, stage);
   return hipGetLastError();
 }
 
@@ -1339,6 +1533,28 @@ hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixe
     }
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_lu_expand(const DevState& d, const LuArgs& lu, int stage, int c0, int count, double* X,
+                            hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  switch (d.N) {
+    case 16: return launch_lu_t<16>(d, lu, stage, c0, count, X, s);
+    case 24: return launch_lu_t<24>(d, lu, stage, c0, count, X, s);
+    case 32: return launch_lu_t<32>(d, lu, stage, c0, count, X, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_lu_diag(const DevState& d, const double* pq, double* dinv, hipStream_t s) {
+  if (d.n_cells <= 0) return hipSuccess;
+  switch (d.N) {
+    case 16: hipLaunchKernelGGL(k_lu_diag<16>, dim3(d.n_cells), dim3(64), 0, s, d, pq, dinv); break;
+    case 24: hipLaunchKernelGGL(k_lu_diag<24>, dim3(d.n_cells), dim3(64), 0, s, d, pq, dinv); break;
+    case 32: hipLaunchKernelGGL(k_lu_diag<32>, dim3(d.n_cells), dim3(64), 0, s, d, pq, dinv); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_expand_plain(int N, int count, int CS, const double* core, const double* fac,

@@ -20,7 +20,7 @@
 
 namespace tk {
 const char* kKernelNames[KID_COUNT] = {"moments", "expand", "gram", "eig", "project", "init",
-                                       "plain_moments", "plain_step", "residual", "rround"};
+                                       "plain_moments", "plain_step", "residual", "rround", "lusgs"};
 }
 
 using namespace tk;
@@ -933,7 +933,177 @@ tk_status state_moments_now(tk_state* st) {
   return ctx_hip(st->ctx, e, "moments");
 }
 
-tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait) {
+// ---------------------------------------------------------------------------
+// LU-SGS implicit iteration (eq. linear-system times dt, diagonal of eq.
+// diagonal_term with the bound of eq. xin-one-rank-approx, divided in rank-1
+// form as eq. one_rank_division): sweep order by a greedy colouring of the
+// face graph (cells in index order, smallest colour no earlier neighbour
+// has), so each colour is one set of passes of independent cells.
+
+static tk_status lu_setup(tk_state* st) {
+  tk_ctx* ctx = st->ctx;
+  const int nc = st->nc, N = st->N, CS = st->CS;
+  std::vector<std::vector<int>> nbrs(nc);
+  for (int k = 0; k < st->ninst; ++k) {
+    const tk_mesh* m = st->meshes[k];
+    const int off = st->inst_off[k];
+    for (int c = 0; c < m->n_cells; ++c)
+      for (int s = 0; s < kSlots; ++s) {
+        const size_t sl = (size_t)c * kSlots + s;
+        if (m->slot_kind[sl] != SK_INTERIOR) continue;
+        const int g = off + c, nb = off + m->slot_nb[sl];
+        if (nb != g) nbrs[g].push_back(nb);
+      }
+  }
+  std::vector<int> col(nc, -1);
+  int ncol = 0;
+  for (int i = 0; i < nc; ++i) {
+    std::vector<char> taken(nbrs[i].size() + 1, 0);
+    for (int m : nbrs[i])
+      if (col[m] >= 0 && col[m] < (int)taken.size()) taken[col[m]] = 1;
+    int c = 0;
+    while (taken[c]) ++c;
+    col[i] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  std::vector<int> fw, bw;
+  st->lu_off.assign(ncol + 1, 0);
+  st->lu_boff.assign(ncol + 1, 0);
+  std::vector<int> cnt(ncol, 0), bcnt(ncol, 0);
+  for (int k = 0; k < ncol; ++k) {
+    for (int i = 0; i < nc; ++i) {
+      if (col[i] != k) continue;
+      fw.push_back(i);
+      bool later = false;
+      for (int m : nbrs[i]) later = later || col[m] > k;
+      if (later) bw.push_back(i);
+    }
+    st->lu_off[k + 1] = (int)fw.size();
+    st->lu_boff[k + 1] = (int)bw.size();
+    cnt[k] = st->lu_off[k + 1] - st->lu_off[k];
+    bcnt[k] = st->lu_boff[k + 1] - st->lu_boff[k];
+  }
+  // (p, Q) of the mode-1 unfolding of |xi| per instance
+  std::vector<double> pq((size_t)st->ninst * (N + N * N), 0.0);
+  for (int k = 0; k < st->ninst; ++k) {
+    const InstParams& P = st->ip_host[k];
+    std::vector<double> S((size_t)N * N * N);
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j)
+        for (int l = 0; l < N; ++l) {
+          const double x = P.xi_min + i * P.dxi, y = P.xi_min + j * P.dxi, z = P.xi_min + l * P.dxi;
+          S[((size_t)i * N + j) * N + l] = std::sqrt(x * x + y * y + z * z);
+        }
+    double* p = pq.data() + (size_t)k * (N + N * N);
+    double* Q = p + N;
+    for (int i = 0; i < N; ++i) {
+      double s = 0.0;
+      for (int o = 0; o < N * N; ++o) s += S[(size_t)i * N * N + o];
+      p[i] = s;
+      for (int i2 = 0; i2 < N; ++i2) {
+        double q = 0.0;
+        for (int o = 0; o < N * N; ++o) q += S[(size_t)i * N * N + o] * S[(size_t)i2 * N * N + o];
+        Q[i * N + i2] = q;
+      }
+    }
+  }
+  tk_status s = TK_OK;
+  auto take = [&](size_t bytes) -> void* { return s == TK_OK ? st_alloc(st, std::max<size_t>(bytes, 4), &s) : nullptr; };
+  st->d_lu_col = (int*)take(sizeof(int) * nc);
+  st->d_lu_cells = (int*)take(sizeof(int) * nc);
+  st->d_lu_bcells = (int*)take(sizeof(int) * bw.size());
+  st->d_lu_cnt = (int*)take(sizeof(int) * ncol);
+  st->d_lu_bcnt = (int*)take(sizeof(int) * ncol);
+  st->d_df_core = (double*)take(sizeof(double) * (size_t)nc * CS * CS * CS);
+  st->d_df_fac = (double*)take(sizeof(double) * (size_t)nc * 3 * CS * N);
+  st->d_df_rank = (int*)take(sizeof(int) * (size_t)nc * 3);
+  st->d_lu_dinv = (double*)take(sizeof(double) * (size_t)nc * (N + 1));
+  st->d_lu_pq = (double*)take(sizeof(double) * pq.size());
+  if (s != TK_OK) return s;
+  hipError_t e = hipMemcpy(st->d_lu_col, col.data(), sizeof(int) * nc, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(st->d_lu_cells, fw.data(), sizeof(int) * nc, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !bw.empty())
+    e = hipMemcpy(st->d_lu_bcells, bw.data(), sizeof(int) * bw.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(st->d_lu_cnt, cnt.data(), sizeof(int) * ncol, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(st->d_lu_bcnt, bcnt.data(), sizeof(int) * ncol, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(st->d_lu_pq, pq.data(), sizeof(double) * pq.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "LU-SGS set-up");
+  st->lu_ready = true;
+  return TK_OK;
+}
+
+// One LU-SGS iteration: moments, rank-1 diagonals, forward sweep (df* by
+// colour, ascending), backward sweep (df by colour, descending, only cells
+// with a later neighbour), commit f + df into the next buffers.  Every stage
+// is an N-basis FP64 rounding of the stage's expanded tensor.
+static tk_status state_lu_iteration(tk_state* st) {
+  tk_ctx* ctx = st->ctx;
+  hipStream_t q = ctx->stream;
+  hipEvent_t ev;
+  hipError_t e;
+  DevState d = state_dev(st);
+  prof_begin(ctx, KID_MOMENTS, &ev);
+  e = launch_moments(d, q);
+  prof_end(ctx, KID_MOMENTS, ev);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "moments");
+  prof_begin(ctx, KID_LU, &ev);
+  e = launch_lu_diag(d, st->d_lu_pq, st->d_lu_dinv, q);
+  prof_end(ctx, KID_LU, ev);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "LU-SGS diagonal");
+  LuArgs lu{st->d_df_core, st->d_df_fac, st->d_df_rank, st->d_lu_col, 0, st->d_lu_dinv};
+  double* X = (double*)st->X;
+  // one stage over the listed cells (cells == nullptr: every cell), rounded
+  // into (fac_o, rank_o, core_o)
+  auto stage = [&](int kind, int count, const int* cells, const int* cells_n, double* fac_o, int* rank_o,
+                   double* core_o) -> tk_status {
+    DevState ds = d;
+    ds.cells = cells;
+    ds.cells_n = cells_n;
+    for (int c0 = 0; c0 < count; c0 += st->chunk) {
+      const int cnt = std::min(st->chunk, count - c0);
+      prof_begin(ctx, KID_LU, &ev);
+      e = launch_lu_expand(ds, lu, kind, c0, cnt, X, q);
+      prof_end(ctx, KID_LU, ev);
+      if (e != hipSuccess) return ctx_hip(ctx, e, "LU-SGS stage");
+      prof_begin(ctx, KID_GRAM, &ev);
+      e = launch_gram(st->N, cnt, X, 0, st->G, q, c0, cells_n);
+      prof_end(ctx, KID_GRAM, ev);
+      if (e != hipSuccess) return ctx_hip(ctx, e, "gram");
+      prof_begin(ctx, KID_EIG, &ev);
+      e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, fac_o, rank_o, nullptr, st->Wb,
+                     nullptr, 1e-15, 1e-18, q, 0.0, nullptr, 0, cells, cells_n, nullptr);
+      if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, X, 0, st->Wb, st->G, q, c0, cells_n);
+      if (e == hipSuccess)
+        e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, fac_o, rank_o, st->Wb, nullptr,
+                       nullptr, 1e-15, 1e-18, q, 0.0, nullptr, 0, cells, cells_n, nullptr);
+      prof_end(ctx, KID_EIG, ev);
+      if (e != hipSuccess) return ctx_hip(ctx, e, "eig");
+      prof_begin(ctx, KID_PROJECT, &ev);
+      e = launch_project(st->N, cnt, X, 0, c0, st->CS, fac_o, rank_o, core_o, q, cells, cells_n);
+      prof_end(ctx, KID_PROJECT, ev);
+      if (e != hipSuccess) return ctx_hip(ctx, e, "project");
+    }
+    return TK_OK;
+  };
+  const int ncol = (int)st->lu_off.size() - 1;
+  tk_status s = TK_OK;
+  for (int k = 0; k < ncol && s == TK_OK; ++k) {
+    lu.colour = k;
+    s = stage(LU_FORWARD, st->lu_off[k + 1] - st->lu_off[k], st->d_lu_cells + st->lu_off[k], st->d_lu_cnt + k,
+              st->d_df_fac, st->d_df_rank, st->d_df_core);
+  }
+  for (int k = ncol - 1; k >= 0 && s == TK_OK; --k) {
+    lu.colour = k;
+    s = stage(LU_BACKWARD, st->lu_boff[k + 1] - st->lu_boff[k], st->d_lu_bcells + st->lu_boff[k],
+              st->d_lu_bcnt + k, st->d_df_fac, st->d_df_rank, st->d_df_core);
+  }
+  if (s == TK_OK) s = stage(LU_COMMIT, st->nc, nullptr, nullptr, d.fac_n, d.rank_n, d.core_n);
+  if (s != TK_OK) return s;
+  st->cur ^= 1;
+  return TK_OK;
+}
+
+tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait, bool lusgs) {
   tk_ctx* ctx = st->ctx;
   hipStream_t q = ctx->stream;
   tk_status s;
@@ -944,7 +1114,7 @@ tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait) {
                                     hipMemcpyDeviceToDevice, q);
       if (e != hipSuccess) return ctx_hip(ctx, e, "macro copy");
     }
-    if ((s = state_step(st)) != TK_OK) return s;
+    if ((s = lusgs ? state_lu_iteration(st) : state_step(st)) != TK_OK) return s;
   }
   if (!wait) return TK_OK;
   if ((s = state_moments_now(st)) != TK_OK) return s;
@@ -1408,6 +1578,19 @@ tk_status tk_step(tk_state* st, int32_t nsteps, double* residual) {
   if (!st || nsteps < 0) return TK_EINVAL;
   std::lock_guard<std::recursive_mutex> g(st->ctx->mu);
   return state_steps(st, nsteps, residual, true);
+}
+
+tk_status tk_lusgs(tk_state* st, int32_t iters, double* residual) {
+  if (!st || iters < 0) return TK_EINVAL;
+  tk_ctx* ctx = st->ctx;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  if (st->plain || st->mixed || st->oblique || st->N > 32)
+    return ctx_fail(ctx, TK_EINVAL, "LU-SGS runs on FP64 Tucker states with N <= 32 and axis-aligned faces");
+  if (!st->lu_ready) {
+    const tk_status s = lu_setup(st);
+    if (s != TK_OK) return s;
+  }
+  return state_steps(st, iters, residual, true, true);
 }
 
 tk_status tk_step_async(tk_state* st, int32_t nsteps) {

@@ -76,9 +76,21 @@ struct DevState {
   const int* cells_n;
 };
 
+// LU-SGS sweeps: the increments (state layout) of the cells already swept,
+// the sweep colour of every cell and the rank-1 inverse diagonal.
+struct LuArgs {
+  const double* core;  // [nc][CS^3]
+  const double* fac;   // [nc][3][CS][N]
+  const int* rank;     // [nc][3]
+  const int* col;      // [nc]
+  int colour;          // colour of the cells of the launch
+  const double* dinv;  // [nc][N + 1]: 1 / u(i) for i < N, then 1 / sigma
+};
+enum LuStage { LU_FORWARD = 0, LU_BACKWARD = 1, LU_COMMIT = 2 };
+
 // Kernel families (names used by the profiler interface).
 enum KernelId { KID_MOMENTS = 0, KID_EXPAND, KID_GRAM, KID_EIG, KID_PROJECT, KID_INIT, KID_PLAIN_MOM,
-                KID_PLAIN_STEP, KID_RESID, KID_RROUND, KID_COUNT };
+                KID_PLAIN_STEP, KID_RESID, KID_RROUND, KID_LU, KID_COUNT };
 extern const char* kKernelNames[KID_COUNT];
 
 // ---- launchers (each enqueues on `s`) -------------------------------------
@@ -121,6 +133,16 @@ hipError_t launch_rround(const DevState& d, int* listD, int* nD, int* wvalid, un
                          hipStream_t s);
 // p[0..n) = v
 hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s);
+// Rank-1 truncated HOSVD u (x) u (x) u sigma of every cell's LU-SGS diagonal
+// (1 + dt nu) 1 + (dt / (2 V)) (sum_l A_l) |xi|; pq[inst] = (p, Q) of |xi|'s
+// mode-1 unfolding S: p = S 1 (N values), Q = S S^T (N x N)
+hipError_t launch_lu_diag(const DevState& d, const double* pq, double* dinv, hipStream_t s);
+// LU-SGS stage of `count` cells (d.cells / d.cells_n from c0) into X (fp64):
+// forward  X = D^-1 (dt R + sum_{lower far cells} b_l o df*_m)
+// backward X = df*_i + D^-1 sum_{upper far cells} b_l o df_m
+// commit   X = f_i + df_i
+hipError_t launch_lu_expand(const DevState& d, const LuArgs& lu, int stage, int c0, int count, double* X,
+                            hipStream_t s);
 // generic expansion of `count` Tucker tensors given in the state layout into X (fp64)
 hipError_t launch_expand_plain(int N, int count, int CS, const double* core, const double* fac,
                                const int* rank, double* X, hipStream_t s);

@@ -135,6 +135,22 @@ struct tk_state {
   unsigned long long* d_rstats = nullptr;
   int* h_rcnt = nullptr;
   long long dense_total = 0;  // cells rounded on the N-basis path (eager steps)
+  // LU-SGS (set up on first use): sweep colour of every cell, the cells of
+  // each colour (forward) and those of each colour with a later neighbour
+  // (backward), the increments df* / df in the state layout, the rank-1
+  // inverse diagonals and (p, Q) of |xi| per instance
+  bool lu_ready = false;
+  std::vector<int> lu_off, lu_boff;
+  int* d_lu_col = nullptr;
+  int* d_lu_cells = nullptr;
+  int* d_lu_bcells = nullptr;
+  int* d_lu_cnt = nullptr;
+  int* d_lu_bcnt = nullptr;
+  double* d_df_core = nullptr;
+  double* d_df_fac = nullptr;
+  int* d_df_rank = nullptr;
+  double* d_lu_dinv = nullptr;
+  double* d_lu_pq = nullptr;
   double* Wb = nullptr;     // first-pass bases of the FP64 refinement
   double* Wkeep = nullptr;  // [nc][3][N][N] previous full eigenbases (warm start)
   bool warm = false;        // Wkeep holds real bases (after the first step)
@@ -149,7 +165,7 @@ tk_status ctx_hip(tk_ctx* ctx, hipError_t e, const char* what);
 int face_axis(const double* e);
 void* ctx_alloc(tk_ctx* ctx, size_t bytes, tk_status* st);
 void ctx_free(tk_ctx* ctx, void* p);
-tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait);
+tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait, bool lusgs = false);
 size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk);
 void state_tune_begin(tk_state* st);
 tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag);

@@ -26,7 +26,7 @@ EXPORTED = [
     "tk_ctx_create", "tk_ctx_destroy", "tk_last_error", "tk_sync", "tk_prof_enable", "tk_prof_get",
     "tk_prof_reset", "tk_prof_eig", "tk_mesh_load", "tk_mesh_destroy", "tk_state_init", "tk_state_init_batch",
     "tk_state_destroy", "tk_state_info", "tk_state_dt", "tk_state_set_chunk", "tk_state_chunk",
-    "tk_state_tune", "tk_state_use_graph", "tk_state_streams", "tk_state_rounding", "tk_state_checkpoint", "tk_state_restore", "tk_moments", "tk_step", "tk_step_async",
+    "tk_state_tune", "tk_state_use_graph", "tk_state_streams", "tk_state_rounding", "tk_state_checkpoint", "tk_state_restore", "tk_moments", "tk_step", "tk_step_async", "tk_lusgs",
     "tk_state_ranks", "tk_state_export", "tk_round", "tk_round_tucker", "tk_round_tucker_noalloc",
     "tk_plain_init", "tk_ctx_create_ex",
     "tk_serve_create",
@@ -121,6 +121,7 @@ def lib():
             "tk_state_restore": [P, C.c_void_p, C.c_size_t],
             "tk_moments": [P, C.POINTER(C.c_double)],
             "tk_step": [P, C.c_int32, C.POINTER(C.c_double)],
+            "tk_lusgs": [P, C.c_int32, C.POINTER(C.c_double)],
             "tk_step_async": [P, C.c_int32],
             "tk_state_ranks": [P, C.POINTER(C.c_int32), C.POINTER(C.c_double)],
             "tk_state_export": [P, C.c_int32, C.POINTER(tk_tucker)],
@@ -390,6 +391,12 @@ class State:
     def step(self, n=1, residual=False):
         res = np.zeros(self.n_instances) if residual else None
         _check(lib().tk_step(self.h, int(n), _dptr(res) if residual else None), self.ctx.h)
+        return res
+
+    def lusgs(self, n=1, residual=False):
+        """tk_lusgs: n LU-SGS implicit iterations."""
+        res = np.zeros(self.n_instances) if residual else None
+        _check(lib().tk_lusgs(self.h, int(n), _dptr(res) if residual else None), self.ctx.h)
         return res
 
     def step_async(self, n=1):
