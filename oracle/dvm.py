@@ -8,6 +8,11 @@ eq. exact-flux literally, form f* = f + dt R (eq. expl-scheme-final, Alg. 1),
 then round f* with Op1 (LAPACK SVD of the three unfoldings).  One rounding
 per cell per step, applied to the exact full update, is the reading of the
 paper's "round after operations that grow the ranks".
+
+With exact=True the face fluxes use the exact |xi_n| on every face instead
+of the estimate (on faces off the coordinate axes; on axis faces the two
+coincide): the paper's standard, full-tensor discrete velocity method, the
+baseline of its Table 1.
 """
 
 import numpy as np
@@ -41,7 +46,7 @@ def ghost_full(S, j, Fi):
     raise ValueError(f"unknown boundary kind {kind}")
 
 
-def update_full(S, i, get):
+def update_full(S, i, get, exact=False):
     """f* of cell i from the full tensors returned by get(cell)."""
     mesh = S.mesh
     Fi = get(i)
@@ -54,13 +59,13 @@ def update_full(S, i, get):
         fL = get(L)
         fR = get(Rc) if Rc >= 0 else ghost_full(S, j, fL)
         xn = S.xin_full(j)
-        est = S.estimate_full(j)
+        est = np.abs(xn) if exact else S.estimate_full(j)
         Fj = 0.5 * xn * (fL + fR) - 0.5 * est * (fR - fL)
         R = R - s * (mesh["face_area"][j] / V) * Fj
     return Fi + S.dt * R
 
 
-def step_full(S, F, cells=None, round_result=True):
+def step_full(S, F, cells=None, round_result=True, exact=False):
     """One O1 step.  F: dict or array cell -> full tensor.
 
     Returns dict cell -> (rounded Tucker tensor, or f* when round_result is
@@ -71,7 +76,7 @@ def step_full(S, F, cells=None, round_result=True):
         cells = range(S.mesh["n_cells"])
     out = {}
     for i in cells:
-        X = update_full(S, i, get)
+        X = update_full(S, i, get, exact)
         out[i] = tk.hosvd(X, S.tol, S.cap) if round_result else X
     return out
 
