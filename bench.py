@@ -685,9 +685,7 @@ def main():
     roof = roofline(fam, cfg, mesh, res, window)
     log(f"  roofline ({fam}): {roof}")
     plain = None
-    if oblique:
-        plain = {"value": None, "reason": "the plain comparator covers axis-aligned faces only"}
-    elif not a.no_plain:
+    if not a.no_plain:
         pres = run_gpu(cfg, mesh, m0, a.plain_steps, a.plain_steps, 1, plain=True)
         pv = nc * a.plain_steps / pres["seconds"]
         plain = {"value": pv, "unit": "cell-updates/s", "ms_per_step": 1e3 * pres["seconds"] / a.plain_steps,

@@ -174,6 +174,9 @@ __global__ __launch_bounds__(kPM) void k_plain_step(DevPlain d, int total) {
   __shared__ T s_b[kSlots][N];  // inflow scalings of the six faces
   __shared__ T s_g[kSlots][3][N];  // rank-1 inflow / wall ghost factors
   __shared__ T s_c[8];
+  __shared__ T s_x[N];             // xi_i
+  __shared__ T s_n[kSlots][3];     // outward normals of faces off the axes
+  __shared__ T s_a[kSlots];        // their dt A / V
   __shared__ int s_nb[kSlots];
   __shared__ int8_t s_kind[kSlots], s_axis[kSlots];
   const int pb = blockIdx.x;
@@ -187,7 +190,11 @@ __global__ __launch_bounds__(kPM) void k_plain_step(DevPlain d, int total) {
     s_kind[tid] = d.slot_kind[kSlots * c + tid];
     s_axis[tid] = d.slot_axis[kSlots * c + tid];
     s_nb[tid] = d.slot_nb[kSlots * c + tid];
+    s_a[tid] = (T)d.slot_coef[kSlots * c + tid];
+    for (int a = 0; a < 3; ++a)
+      s_n[tid][a] = (d.slot_nrm && s_axis[tid] < 0) ? (T)d.slot_nrm[3 * (kSlots * c + tid) + a] : (T)0;
   }
+  for (int i = tid; i < N; i += kPM) s_x[i] = (T)(P.xi_min + i * P.dxi);
   const double RT = P.Rg * M[4];
   const double nu = d.nu[c];
   for (int o = tid; o < 3 * N; o += kPM) {
@@ -251,6 +258,28 @@ __global__ __launch_bounds__(kPM) void k_plain_step(DevPlain d, int total) {
       const int8_t kind = s_kind[l];
       if (kind == SK_NONE) continue;
       const int a = s_axis[l];
+      if (a < 0) {
+        // a face off the coordinate axes (interior, outflow or free-stream
+        // inflow): the exact upwind split of xi_n = xi . n per node
+        const T n0 = s_n[l][0], coef = s_a[l];
+        const T x23 = s_n[l][1] * s_x[j] + s_n[l][2] * s_x[k];
+        Quad<T> g4;
+        if (kind == SK_INTERIOR) {
+          g4 = load_quad(f + (size_t)s_nb[l] * NE + 4 * (size_t)g);
+        } else if (kind == SK_OUTFLOW) {
+          g4 = own;
+        } else {
+          const T g23 = s_g[l][1][j] * s_g[l][2][k];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) g4.v[t] = s_g[l][0][i0 + t] * g23;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const T x = n0 * s_x[i0 + t] + x23;
+          acc.v[t] += x > (T)0 ? -coef * x * own.v[t] : -coef * x * g4.v[t];
+        }
+        continue;
+      }
       T b[4];
       if (a == 0) {
 #pragma unroll

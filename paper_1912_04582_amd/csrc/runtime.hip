@@ -339,6 +339,7 @@ DevPlain plain_dev(const tk_state* st) {
   d.slot_sig = st->d_slot_sig;
   d.slot_coef = st->d_slot_coef;
   d.bc_fac = st->d_bc_fac;
+  d.slot_nrm = st->d_slot_nrm;
   d.f = st->pf[st->cur];
   d.f_n = st->pf[st->cur ^ 1];
   d.macro = st->d_macro;
@@ -409,7 +410,6 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
   std::vector<int> est_inst;     // owning instance of each estimate
   bool oblique = false;
   for (int k = 0; k < count; ++k) oblique |= meshes[k]->oblique;
-  if (oblique && plain) return ctx_fail(ctx, TK_EINVAL, "plain comparator: faces off the coordinate axes are not supported");
   st->inst_off.assign(count + 1, 0);
   int c0 = 0, b0 = 0;
   for (int k = 0; k < count; ++k) {

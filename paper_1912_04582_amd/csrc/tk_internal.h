@@ -161,6 +161,7 @@ struct DevPlain {
   const int8_t* slot_sig;
   const double* slot_coef;
   const double* bc_fac;
+  const double* slot_nrm;  // [nc][6][3] outward normals (faces off the axes), or nullptr
   const void* f;   // [nc][N^3] float or double
   void* f_n;
   double* macro;
