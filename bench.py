@@ -4,16 +4,24 @@ Workload (default): the channel flow with an obstacle -- 64x32x32 lattice
 minus an 8^3 obstacle (65,024 hex cells), Mach-2 inflow, zero-gradient
 outflow, symmetry sides, diffuse walls at T_w = 1; velocity grid 32^3 on
 [-6, 6]^3; rank cap 12, rounding tolerance 1e-5; mixed precision (FP32
-term assembly, FP64 Gram/eigen/projection/moments).  A step is one pass of
-the whole hot path over every cell: moments, f_S, boundary ghosts, flux
-terms, truncated-HOSVD rounding.  Inputs are resident in HBM before the
-timed region; the timed region is `--steps` steps from the initial state
-after `--warmup` steps on a scratch state.
+N-basis term assembly; FP64 factor-space rounding, Grams, eigensolves,
+projection and moments); 200 steps.  A step is one pass of the whole hot
+path over every cell: moments, f_S, boundary ghosts, flux terms,
+truncated-HOSVD rounding.  Inputs are resident in HBM before the timed
+region.  The state advances the workload's 200 steps; the timed region is
+the last `--steps` of them (default all, after `--warmup` steps), with no
+per-kernel events; `--steps 20` times steps 180-200, where the ranks are
+highest.
 
-One JSON line on stdout:  metric/value (cell-updates/s), roofline of the
-dominant kernel family (HIP events on the library stream), the plain
-full-tensor GPU step on the same workload, a sampled parity check against
-the FP64 oracle and the oracle's own CPU throughput (`cpu_baseline`).
+One JSON line on stdout: metric/value (cell-updates/s over the timed
+window); per-kernel times and the roofline of the dominant kernel family
+from five further steps with every pass on one stream and HIP events around
+each launch; the plain full-tensor GPU step on the same workload; the FP64
+path timed on the same window and the mixed path's end-of-run macro error
+against it, beside the FP64 path's own spread under a 1e-7 input
+perturbation; LU-SGS iterations against explicit FP64 steps; a sampled
+parity check against the FP64 oracle and the oracle's own CPU throughput
+(`cpu_baseline`, one single-thread process per host core).
 """
 
 import argparse
@@ -125,17 +133,20 @@ def measured_traffic(workload_name, fam):
     return k["fetch_bytes_per_step"] + k["write_bytes_per_step"]
 
 
-def window_rows(rows, window):
-    """Dispatches of the timed window: from the start of the `window`-th last
-    factor-space (or, without it, moments) launch on; rows sorted by start."""
+def window_rows(rows, window, tail=0):
+    """Dispatches of the timed window: `window` steps, each opened by a
+    factor-space (or, without it, moments) launch, ending `tail` steps before
+    the last (the per-kernel steps that follow the timed window); rows sorted
+    by start."""
     rows = sorted(rows, key=lambda r: r["start"])
     marks = [r for r in rows if family_of(r["name"]) == "rround"] or \
         [r for r in rows if family_of(r["name"]) == "moments"]
-    t0 = marks[-window]["start"] if len(marks) >= window else rows[0]["start"]
-    return [r for r in rows if r["start"] >= t0]
+    t0 = marks[-(window + tail)]["start"] if len(marks) >= window + tail else rows[0]["start"]
+    t1 = marks[-tail]["start"] if tail and len(marks) >= tail else float("inf")
+    return [r for r in rows if t0 <= r["start"] < t1]
 
 
-def trace_summary(trace_csv, window, bench_json=None):
+def trace_summary(trace_csv, window, bench_json=None, tail=5):
     """Markdown table of kernel-family times in the timed window of a
     rocprofv3 --kernel-trace CSV, beside the HIP-event averages of the bench
     line when given."""
@@ -145,7 +156,7 @@ def trace_summary(trace_csv, window, bench_json=None):
         for r in csv.DictReader(fh):
             rows.append({"name": r["Kernel_Name"], "start": int(r["Start_Timestamp"]),
                          "end": int(r["End_Timestamp"])})
-    win = window_rows(rows, window)
+    win = window_rows(rows, window, tail)
     fam = {}
     for r in win:
         f = family_of(r["name"])
@@ -157,7 +168,7 @@ def trace_summary(trace_csv, window, bench_json=None):
     if bench_json:
         with open(bench_json) as fh:
             b = json.loads(fh.read().strip().splitlines()[-1])
-        for f, ms in b.get("kernel_ms_per_step", {}).items():
+        for f, ms in b.get("kernel_ms_per_step_one_stream", b.get("kernel_ms_per_step", {})).items():
             hip[f] = ms
     out = ["| family | launches | total (ms) | per step (ms) | average per launch (ms) | HIP events, per step (ms) |",
            "|---|---|---|---|---|---|"]
@@ -187,7 +198,7 @@ def counter_rows(csv_path, counter):
     return sorted(agg.values(), key=lambda r: r["id"])
 
 
-def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, window, workload_name):
+def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, window, workload_name, tail=5):
     """Bytes per step of each kernel family in the timed window (the sum over
     its launches there, divided by the window's steps: independent of how the
     step splits its cells into launches): FETCH_SIZE and WRITE_SIZE (KiB per
@@ -207,11 +218,12 @@ def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, window
         rows = counter_rows(fetch_csv if counter == "FETCH_SIZE" else write_csv, counter)
         marks = [r for r in rows if family_of(r["name"]) == "rround"] or \
             [r for r in rows if family_of(r["name"]) == "moments"]
-        i0 = marks[-window]["id"] if len(marks) >= window else rows[0]["id"]
+        i0 = marks[-(window + tail)]["id"] if len(marks) >= window + tail else rows[0]["id"]
+        i1 = marks[-tail]["id"] if tail and len(marks) >= tail else float("inf")
         fam = {}
         for r in rows:
             f = family_of(r["name"])
-            if f and r["id"] >= i0:
+            if f and i0 <= r["id"] < i1:
                 t = fam.setdefault(f, [0.0, 0, set()])
                 t[0] += r["value"] * 1024.0 * scale
                 t[1] += 1
@@ -237,7 +249,7 @@ def roofline(fam, cfg, mesh, res, steps):
         return None
     per_launch_s = ms / 1e3 / launches
     launches_per_step = launches / steps
-    rp = res.get("rounding_paths") or {}
+    rp = res.get("prof_paths") or {}
     nb = rp.get("nbasis", nc * steps) / steps  # N-basis cells per step
     r_avg = 0.5 * (res["ranks0"].astype(np.float64) + res["ranks1"].astype(np.float64))
     frac_nb = nb / nc
@@ -357,10 +369,16 @@ def macro_rel_err(a, b, Rg=0.5, m=1.0):
     return float(e)
 
 
-def run_gpu(cfg, mesh, m0, total, window, warmup, plain=False, prof=True, one_stream=False, tune=True):
+def run_gpu(cfg, mesh, m0, total, window, warmup, plain=False, prof=True, one_stream=False, tune=True,
+            prof_steps=5):
     """Advance a state `total` steps from the initial fields and time the
     last `window` of them (after at least `warmup` untimed steps on the same
-    state).  Pass-size trials run first on a throw-away state."""
+    state), with no per-kernel events in the timed region.  Pass-size trials
+    run first on a throw-away state.  With `prof`, `prof_steps` further steps
+    follow with every rounding pass on the context stream and HIP events
+    around every launch: the per-kernel times, rounding-path counts,
+    eigensolver counters and ranks of that window feed the roofline (one
+    kernel at a time, so no launch shares the device with another pass)."""
     window = min(window, total)
     pre = max(warmup, total - window)
     ctx = tk.Context(0)
@@ -386,32 +404,45 @@ def run_gpu(cfg, mesh, m0, total, window, warmup, plain=False, prof=True, one_st
         if pre:
             st.step(pre)
         ctx.sync()
-        ctx.prof_reset()
-        ctx.prof_enable(prof)
-        ctx.eig_stats(reset=True)
+        ctx.prof_enable(False)
         if not plain:
             st.rounding()
-        r0 = None if plain else st.ranks()[0]
         t0 = time.perf_counter()
         st.step(window)  # waits for completion
         t1 = time.perf_counter()
-        ctx.prof_enable(False)
-        fams = ["moments", "rround", "expand", "gram", "eig", "project"] if not plain else ["plain_moments", "plain_step"]
-        prof_ms = {f: ctx.prof_get(f) for f in fams}
-        eig = ctx.eig_stats(reset=True)
         rcount = None
         if not plain:
             rcount = st.rounding()
-            log(f"  eigensolver (N-basis path): {eig}")
             log(f"  rounding paths over the window (cell-updates): {rcount}")
-        r1, C = (None, None) if plain else st.ranks()
+        rmain, C = (None, None) if plain else st.ranks()
         final = st.moments()
+        prof_ms, eig, pcount, r0, r1, pw = {}, None, None, None, None, 0
+        if prof:
+            pw = prof_steps
+            if not plain:
+                st.streams(False)
+                st.rounding()
+                r0 = st.ranks()[0]
+            ctx.eig_stats(reset=True)
+            ctx.prof_reset()
+            ctx.prof_enable(True)
+            st.step(pw)
+            ctx.prof_enable(False)
+            fams = ["moments", "rround", "expand", "gram", "eig", "project"] if not plain else \
+                ["plain_moments", "plain_step"]
+            prof_ms = {f: ctx.prof_get(f) for f in fams}
+            eig = ctx.eig_stats(reset=True)
+            if not plain:
+                pcount = st.rounding()
+                r1 = st.ranks()[0]
+                log(f"  per-kernel window ({pw} steps, one stream): eigensolver {eig}, rounding paths {pcount}")
         st.close()
         tm.close()
     finally:
         ctx.close()
-    return dict(seconds=t1 - t0, prof=prof_ms, ranks0=r0, ranks1=r1, compression=C, rounding_paths=rcount,
-                final=final, pre=pre, window=window, two_streams=two, eig_stats=None if plain else eig)
+    return dict(seconds=t1 - t0, prof=prof_ms, prof_steps=pw, ranks0=r0, ranks1=r1, ranks_end=rmain,
+                compression=C, rounding_paths=rcount, prof_paths=pcount, final=final, pre=pre, window=window,
+                two_streams=two, eig_stats=eig)
 
 
 def run_batch(steps, warmup, count, prof_steps=3):
@@ -464,6 +495,43 @@ def run_batch(steps, warmup, count, prof_steps=3):
                 groups={N: (len(v), sum(m["n_cells"] for _, m, _ in v)) for N, v in groups.items()})
 
 
+def run_lusgs(cfg, mesh, m0, iters, cfl):
+    """LU-SGS iterations (FP64, CFL `cfl`) against explicit FP64 steps (the
+    workload's CFL) from the same initial state: time per iteration, the
+    kernel families of one more iteration, and the residual per iteration."""
+    c64 = dict(cfg, precision="fp64")
+    out = {}
+    ctx = tk.Context(0)
+    try:
+        tm = tk.Mesh(ctx, mesh)
+        for kind, c in (("lusgs", dict(c64, cfl=cfl)), ("explicit", c64)):
+            st = tk.State(ctx, tm, c, m0)
+            st.streams(False)
+            go = st.lusgs if kind == "lusgs" else st.step
+            go(1)  # untimed: set-up (colouring, buffers) and first rounding
+            res = []
+            t0 = time.perf_counter()
+            for _ in range(iters):
+                res.append(float(go(1, residual=True)[0]))
+            t1 = time.perf_counter()
+            ctx.prof_reset()
+            ctx.prof_enable(True)
+            go(1)
+            ctx.prof_enable(False)
+            fams = ["moments", "lusgs", "expand", "gram", "eig", "project", "rround"]
+            out[kind] = {"ms_per_iteration": 1e3 * (t1 - t0) / iters, "iterations": iters, "cfl": c["cfl"],
+                         "residual_per_iteration": res,
+                         "kernel_ms_one_iteration": {f: ctx.prof_get(f)[0] for f in fams if ctx.prof_get(f)[1]}}
+            log(f"{kind}: {out[kind]['ms_per_iteration']:.2f} ms per iteration at CFL {c['cfl']}, "
+                f"residuals {['%.2e' % r for r in res]}")
+            st.close()
+        tm.close()
+    finally:
+        ctx.close()
+    out["cost_ratio"] = out["lusgs"]["ms_per_iteration"] / out["explicit"]["ms_per_iteration"]
+    return out
+
+
 def serve_run(reqs, rate, seed=5):
     """Submit requests (arrivals at t = 0 when rate is None, else Poisson with
     `rate` per second), wait for all; latency = t_done - t_arrive."""
@@ -491,12 +559,13 @@ def serve_run(reqs, rate, seed=5):
                         f"latency {r['t_done'] - r['t_arrive']:.2f} s ({len(done)}/{len(tickets)} done)")
         time.sleep(0.002)
     t1 = time.perf_counter()
+    stats = srv.stats()
     srv.close()
     ctx.close()
     res = [done[t] for t in tickets]
     lat = np.array([r["t_done"] - r["t_arrive"] for r in res])
     updates = sum(r["steps"] * q[0]["n_cells"] for r, q in zip(res, reqs))
-    return dict(seconds=t1 - t0, latency=lat, updates=updates,
+    return dict(seconds=t1 - t0, latency=lat, updates=updates, stats=stats,
                 status=[r["status"] for r in res], steps=[r["steps"] for r in res])
 
 
@@ -569,6 +638,9 @@ def main():
     ap.add_argument("--parity-cells", type=int, default=None)
     ap.add_argument("--no-fp64-check", action="store_true",
                     help="skip the FP64 GPU run used for the end-of-run mixed-precision error")
+    ap.add_argument("--no-lusgs", action="store_true", help="skip the LU-SGS iteration timing")
+    ap.add_argument("--lusgs-iters", type=int, default=4)
+    ap.add_argument("--lusgs-cfl", type=float, default=4.0)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-count", type=int, default=12)
     ap.add_argument("--serve-max-steps", type=int, default=100)
@@ -612,7 +684,7 @@ def main():
         sys.exit(2)
     if a.workload == "serve":
         r = run_serve(a.serve_count, a.serve_max_steps)
-        out = {"metric": "Tucker S-model cell-updates/s (vs plain GPU step at 1e-5 rel err); p50/p99 latency",
+        out = {"metric": "served Tucker S-model cell-updates/s; p50/p99 request latency",
                "unit": "cell-updates/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None, "dtype": "f32 terms + f64 rounding", "data": "synthetic",
                "config": {"workload": f"serving {a.serve_count} jittered-box requests",
@@ -622,7 +694,8 @@ def main():
             out[key] = {"value": q["updates"] / q["seconds"], "seconds": q["seconds"],
                         "p50_latency_s": float(np.percentile(q["latency"], 50)),
                         "p99_latency_s": float(np.percentile(q["latency"], 99)),
-                        "statuses": sorted(set(q["status"])), "steps": q["steps"]}
+                        "statuses": sorted(set(q["status"])), "steps": q["steps"],
+                        "shared_launches": q["stats"]}
             log(f"serve {key}: {out[key]['value']:.4g} cell-updates/s, p50 {out[key]['p50_latency_s']:.2f} s, "
                 f"p99 {out[key]['p99_latency_s']:.2f} s over {q['seconds']:.1f} s")
         out["arrival_rate_per_s"] = r["rate"]
@@ -648,7 +721,7 @@ def main():
         for f, (ms, n) in r["prof"].items():
             log(f"  {f:10s} {ms:10.2f} ms total over {n} launches ({r['prof_steps']} eager profiled steps)")
         print(json.dumps({
-            "metric": "Tucker S-model cell-updates/s (vs plain GPU step at 1e-5 rel err)", "value": value,
+            "metric": "batched Tucker S-model cell-updates/s", "value": value,
             "unit": "cell-updates/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup,
             "ms_per_step": 1e3 * r["seconds"] / steps, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32 terms + f64 rounding", "data": "synthetic",
@@ -676,13 +749,13 @@ def main():
     log(f"tucker: {ms_step:.2f} ms/step over steps {res['pre']}..{res['pre'] + window}, {value:.4g} cell-updates/s, "
         f"mean compression {res['compression']:.4g}")
     for f, (ms, n) in res["prof"].items():
-        log(f"  {f:10s} {ms:10.2f} ms total over {n} launches")
-    r1 = res["ranks1"]
+        log(f"  {f:10s} {ms / res['prof_steps']:8.3f} ms/step over {n} launches (one stream, events)")
+    r1 = res["ranks_end"]
     rmax = r1.max(1)
     log("  final max-rank histogram:", np.bincount(rmax, minlength=cfg["cap"] + 1).tolist())
     log(f"  mean rank {r1.mean():.2f}")
     fam, (fms, fn) = max(res["prof"].items(), key=lambda kv: kv[1][0])
-    roof = roofline(fam, cfg, mesh, res, window)
+    roof = roofline(fam, cfg, mesh, res, res["prof_steps"])
     log(f"  roofline ({fam}): {roof}")
     plain = None
     if not a.no_plain:
@@ -690,7 +763,7 @@ def main():
         pv = nc * a.plain_steps / pres["seconds"]
         plain = {"value": pv, "unit": "cell-updates/s", "ms_per_step": 1e3 * pres["seconds"] / a.plain_steps,
                  "steps": a.plain_steps, "storage": "N^3 values per cell",
-                 "kernel_ms_per_step": {f: ms / a.plain_steps for f, (ms, n) in pres["prof"].items()}}
+                 "kernel_ms_per_step": {f: ms / pres["prof_steps"] for f, (ms, n) in pres["prof"].items()}}
         log(f"plain: {plain['ms_per_step']:.2f} ms/step, {pv:.4g} cell-updates/s")
     cpu = parity = None
     if not a.no_cpu:
@@ -734,6 +807,9 @@ def main():
                "fp64_input_perturbation_1e-7_spread": floor, "bar": 1e-5, "within_bar": bool(e_end <= 1e-5)}
         log(f"end of run: mixed vs FP64 path after {total} steps: {e_end:.3e} "
             f"(FP64 with inputs perturbed by 1e-7: {floor:.3e})")
+    lu = None
+    if not a.no_lusgs and N <= 32 and not oblique:
+        lu = run_lusgs(cfg, mesh, m0, a.lusgs_iters, a.lusgs_cfl)
     out = {
         "metric": "Tucker S-model cell-updates/s vs plain GPU step; macro error vs the FP64 path stated",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": window, "warmup": res["pre"],
@@ -745,7 +821,9 @@ def main():
                    "timed_window": [res["pre"], res["pre"] + window],
                    "rounding_streams": 2 if res["two_streams"] else 1},
         "dominant_kernel": fam,
-        "kernel_ms_per_step": {f: ms / window for f, (ms, n) in res["prof"].items()},
+        "kernel_ms_per_step_one_stream": {f: ms / res["prof_steps"] for f, (ms, n) in res["prof"].items()},
+        "per_kernel_window": {"steps": res["prof_steps"], "after_step": total,
+                              "how": "every rounding pass on one stream, HIP events around each launch"},
         "rounding_paths_per_step": {k: v / window for k, v in (res["rounding_paths"] or {}).items()},
         "mean_compression": res["compression"],
         "roofline": roof,
@@ -754,6 +832,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "end_of_run": end,
+        "lusgs": lu,
     }
     print(json.dumps(out), flush=True)
 

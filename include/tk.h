@@ -152,9 +152,9 @@ tk_status tk_sync(tk_ctx* ctx);
 tk_status tk_prof_enable(tk_ctx* ctx, int32_t on);
 tk_status tk_prof_get(tk_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
 tk_status tk_prof_reset(tk_ctx* ctx);
-/* Eigensolver counters since the last reset (process-wide): out4[0]
- * matrices solved on the leading block of the previous basis, [1] on the
- * full matrix, [2] Jacobi sweeps, [3] leading-block attempts that fell back.
+/* Eigensolver counters of the N-basis rounding since the last reset
+ * (process-wide): out4[1] matrices solved, [2] Jacobi sweeps run (sweeps
+ * that found nothing to rotate are not counted); [0] and [3] are zero.
  * Synchronises the context stream.                                        */
 tk_status tk_prof_eig(tk_ctx* ctx, int64_t* out4, int32_t reset);
 

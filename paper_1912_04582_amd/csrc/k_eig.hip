@@ -21,13 +21,7 @@
 // Warm start: a cell's Gram changes little from one time step to the next,
 // so the full eigenbasis of the previous step is kept per cell and mode
 // (`Wkeep`); the matrix is first rotated into it (A = W^T G W, V = W) and
-// Jacobi then only removes the small off-diagonal remainder.  With `lead`
-// > 0 only the leading k = r_prev + lead vectors of that basis are used when
-// the rest of the spectrum carries at most 1e-3 of the truncation budget
-// eps^2 trace / 3 (its share then enters the discarded sum); the k x k
-// block W_k^T G W_k is diagonalised and the remaining basis vectors are kept.
-// A rank that comes within 2 of k, or a larger remainder, retries with a
-// block 12 vectors wider, then falls back to the full matrix.  Rounds in
+// Jacobi then only removes the small off-diagonal remainder.  Rounds in
 // which no pair needs a rotation skip the update passes; convergence is
 // checked by a parallel scan of the off-diagonal elements before each sweep.
 //
@@ -51,9 +45,8 @@ constexpr int kEigThreads = 256;
 
 }  // namespace
 
-// Eigensolver statistics: [0] matrices solved on the leading block, [1] on
-// the full matrix, [2] Jacobi sweeps run, [3] leading-block attempts that fell
-// back to the full matrix.
+// Eigensolver statistics: [1] matrices solved, [2] Jacobi sweeps run ([0]
+// and [3] stay zero).
 __device__ unsigned long long g_eig_stats[4];
 
 namespace {
@@ -63,8 +56,8 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
                                                      int c0, double tol_o, int cap_o, int CS, double* fac_n,
                                                      int* rank_n, const double* Win, double* Wout, double* Wkeep,
                                                      double rel_thr, double abs_fac, double drop,
-                                                     const int* rank_prev, int lead, const int* cells,
-                                                     const int* cells_n, int* wvalid) {
+                                                     double tail_frac, const int* cells, const int* cells_n,
+                                                     int* wvalid) {
   constexpr int NT = kEigThreads;
   constexpr int LD = N + 1;
   constexpr int NH = N / 2;
@@ -75,8 +68,7 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
   __shared__ int pp[NH], qq[NH];
   __shared__ int order[N];
   __shared__ int flag[2], s_conv;
-  __shared__ double s_aux;
-  __shared__ int s_rank, s_fast;
+  __shared__ int s_rank;
   const int m = blockIdx.x;
   const int cl = m / 3, mode = m % 3;
   // a pass over a device-side cell list ends at its count
@@ -96,9 +88,8 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
     tol = P.tol;
     cap = P.cap;
   }
-  // the matrix, the previous basis (V[i][j]: entry i of vector j) and the
-  // previous rank, all requested before any is used
-  const int rp = (wr && lead > 0 && rank_prev) ? rank_prev[3 * cell + mode] : 0;
+  // the matrix and the previous basis (V[i][j]: entry i of vector j), both
+  // requested before either is used
   {
     constexpr int PER = (N * N + NT - 1) / NT;
     double ga[PER], wa[PER];
@@ -119,13 +110,6 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
       }
     }
   }
-  // leading block size (N: the full matrix)
-  int k = N;
-  if (wr && lead > 0 && rank_prev) {
-    k = (rp < 1 ? 1 : rp) + lead;
-    k += k & 1;
-    if (k > N) k = N;
-  }
   __syncthreads();
   // trace, reduced by every wave
   double tot = 0.0;
@@ -139,93 +123,10 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
   // off-diagonal floor: abs_fac of the trace, but never above 1e-4 of the
   // truncation budget (a pair that small cannot move energy across the cut)
   const double abs_thr = thr > 0.0 ? fmin(abs_fac * fabs(tot), 1e-4 * thr) : abs_fac * fabs(tot);
-  // up to two leading blocks: r_prev + lead vectors, then 12 more
-  for (int attempt = 0; attempt < 2 && k < N; ++attempt) {
-    // ---- leading block of the previous basis: B = W_k^T G W_k -------------
-    for (int o = lane; o < N * k; o += NT) {
-      const int i = o / k, j = o % k;
-      double s = 0.0;
-      for (int t = 0; t < N; ++t) s += A[i * LD + t] * V[t * LD + j];
-      Tm[i * LD + j] = s;
-    }
-    __syncthreads();
-    for (int o = lane; o < k * k; o += NT) {
-      const int i = o / k, j = o % k;
-      if (j < i) continue;
-      double s = 0.0;
-      for (int t = 0; t < N; ++t) s += V[t * LD + i] * Tm[t * LD + j];
-      A[i * LD + j] = s;  // G is no longer needed on this path
-      A[j * LD + i] = s;
-    }
-    __syncthreads();
-    if (lane == 0) {
-      double tb = 0.0;
-      for (int i = 0; i < k; ++i) tb += A[i * LD + i];
-      const double tail = tot - tb;
-      s_aux = tail > 0.0 ? tail : 0.0;
-      // the rest of the spectrum carries a negligible share of the trace
-      s_fast = (drop == 0.0 && s_aux <= 1e-3 * thr) ? 1 : 0;
-    }
-    __syncthreads();
-    if (s_fast) {
-      for (int o = lane; o < k * k; o += NT) Tm[(o / k) * LD + o % k] = (o / k == o % k) ? 1.0 : 0.0;
-      __syncthreads();
-      jacobi<NT, NH>(A, LD, Tm, LD, k, k, rel_thr, abs_thr, cs, sn, tt, pp, qq, flag, &s_conv, &g_eig_stats[2]);
-      sort_desc<NT>(A, LD + 1, k, order);
-      if (lane == 0) {
-        const int r = choose_rank(A, LD + 1, order, k, s_aux, thr, 0.0, cap);
-        s_rank = r;
-        s_fast = (r <= k - 2) ? 1 : 0;  // keep a margin inside the block
-      }
-      __syncthreads();
-    }
-    if (lane == 0) atomicAdd(&g_eig_stats[s_fast ? 0 : 3], 1ull);
-    if (s_fast) {
-      // new leading vectors W_k V_k (sorted) into A's storage; tail vectors unchanged
-      for (int o = lane; o < N * k; o += NT) {
-        const int i = o / k, j = o % k;
-        double s = 0.0;
-        const int jj = order[j];
-        for (int t = 0; t < k; ++t) s += V[i * LD + t] * Tm[t * LD + jj];
-        A[i * LD + j] = s;
-      }
-      __syncthreads();
-      if (wk) {
-        for (int o = lane; o < N * k; o += NT) {
-          const int j = o / N, i = o % N;
-          wk[j * N + i] = A[i * LD + j];
-        }
-      }
-      const int r = s_rank;
-      if (lane == 0) rank_n[3 * cell + mode] = r;
-      double* out = fac_n + ((size_t)cell * 3 + mode) * CS * N;
-      for (int c = 0; c < CS; ++c) {
-        if (c < r) {
-          if (lane == 0) {
-            double best = -1.0;
-            int bi = 0;
-            for (int i = 0; i < N; ++i) {
-              const double v = fabs(A[i * LD + c]);
-              if (v > best) { best = v; bi = i; }
-            }
-            cs[0] = (A[bi * LD + c] < 0.0) ? -1.0 : 1.0;
-          }
-          __syncthreads();
-          const double sg = cs[0];
-          for (int i = lane; i < N; i += NT) out[c * N + i] = sg * A[i * LD + c];
-          __syncthreads();
-        } else {
-          for (int i = lane; i < N; i += NT) out[c * N + i] = 0.0;
-        }
-      }
-      return;
-    }
-    // fall back to a wider block, then to the full matrix
-    for (int o = lane; o < N * N; o += NT) A[(o / N) * LD + o % N] = g[o];
-    __syncthreads();
-    k += 12;
-    if (k > N) k = N;
-  }
+  // directions whose Rayleigh quotient is below tail_frac of the budget (at
+  // most N of them, together below the budget when tail_frac <= 1/N) are
+  // always discarded: rotations between two of them are skipped
+  const double tail = (drop == 0.0 && thr > 0.0) ? tail_frac * thr : 0.0;
   if (wr) {
     // ---- full warm start: A <- V^T G V through Tm = G V --------------------
     for (int o = lane; o < N * N; o += NT) {
@@ -246,7 +147,7 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
     __syncthreads();
   }
   if (lane == 0) atomicAdd(&g_eig_stats[1], 1ull);
-  jacobi<NT, NH>(A, LD, V, LD, N, N, rel_thr, abs_thr, cs, sn, tt, pp, qq, flag, &s_conv, &g_eig_stats[2]);
+  jacobi<NT, NH>(A, LD, V, LD, N, N, rel_thr, abs_thr, cs, sn, tt, pp, qq, flag, &s_conv, &g_eig_stats[2], tail);
   sort_desc<NT>(A, LD + 1, N, order);
   if (wk) {
     for (int o = lane; o < N * N; o += NT) {
@@ -338,12 +239,12 @@ __global__ void k_identity_basis(int N, size_t count, double* W) {
 hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
                       double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
                       const double* Win, double* Wout, double* Wkeep, double rel_thr, double abs_fac,
-                      hipStream_t s, double drop, const int* rank_prev, int lead, const int* cells,
+                      hipStream_t s, double drop, double tail_frac, const int* cells,
                       const int* cells_n, int* wvalid) {
   if (count <= 0) return hipSuccess;
   dim3 grid(3 * count), blk(kEigThreads);
 #define TK_EIG(NN) hipLaunchKernelGGL(k_eig<NN>, grid, blk, 0, s, G, inst, ip, c0, tol_override, cap_override, CS, \
-                                      fac_n, rank_n, Win, Wout, Wkeep, rel_thr, abs_fac, drop, rank_prev, lead, \
+                                      fac_n, rank_n, Win, Wout, Wkeep, rel_thr, abs_fac, drop, tail_frac, \
                                       cells, cells_n, wvalid)
   switch (N) {
     case 16: TK_EIG(16); break;

@@ -213,11 +213,14 @@ def test_plain_step_on_oblique_faces_matches_exact_flux(ctx, precision, tol):
     assert err < tol, err
 
 
-def test_mixed_long_run_tracks_fp64(ctx):
-    """Many warm-started steps (leading-block and full eigensolves, rank
-    growth near walls): the mixed path stays with the FP64 path.  Rank
-    decisions may differ at the truncation threshold, so the bar is the
-    tolerance-level drift, far above FP32 noise and far below an error."""
+def test_mixed_drift_monitor_against_fp64(ctx):
+    """A drift monitor, not parity evidence (the parity of the mixed path
+    is the oracle tests' 1e-5 over a few steps): after 80 warm-started
+    steps with rank growth near the walls the mixed path stays within 1e-3
+    of the GPU FP64 path.  Rank decisions may differ at the truncation
+    threshold and compound (on the full channel 4.6e-5 after 200 steps,
+    against 3e-7 for the FP64 path's spread under a 1e-7 input
+    perturbation), so this bar only catches a broken mixed path."""
     m, cfg = small_channel(N=24, cap=8, tol=1e-5, precision="mixed", nx=8)
     m0 = synth.initial_macros(cfg, m)
     mesh = tk.Mesh(ctx, m)

@@ -50,24 +50,53 @@ def test_pass_sizes_give_identical_bits(ctx):
     a.close(); b.close(); mesh.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_two_stream_passes_give_identical_bits(precision):
+def handoff_channel():
+    """N = 32 mixed, cap 12, tol 1e-8 from rough fields: most cells exceed
+    the small expansion layout's rank 8 after two steps (the list hand-off
+    of k_expand_pipe), the rest round in factor space or stay small."""
+    m = synth.channel_with_obstacle(nx=8, ny=4, nz=4, h=0.25, obstacle=((3, 5), (1, 3), (1, 3)),
+                                    inflow=(1.0, (0.9, 0.0, 0.0), 1.0), Tw=1.4)
+    cfg = dict(N=32, xi_max=6.0, cap=12, tol=1e-8, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=0.1, Rg=0.5, m=1.0,
+               seed=8, init="random", precision="mixed")
+    return m, cfg, synth.initial_macros(cfg, m)
+
+
+def jittered_case(precision):
+    m = synth.jittered_box(5, 4, 4, 0.2, seed=12)
+    cfg = dict(synth.make_config("cfg0"), N=16, cap=6, tol=1e-6, precision=precision)
+    return m, cfg, synth.initial_macros(cfg, m)
+
+
+TWO_STREAM_CASES = {
+    "box-fp64": lambda: box_case(8, N=16, precision="fp64"),
+    "box-mixed": lambda: box_case(8, N=16, precision="mixed"),
+    "channel-N32-handoff": handoff_channel,
+    "jittered-fp64": lambda: jittered_case("fp64"),
+    "jittered-mixed": lambda: jittered_case("mixed"),
+}
+
+
+@pytest.mark.parametrize("case", list(TWO_STREAM_CASES))
+def test_two_stream_passes_give_identical_bits(case):
     """Rounding passes alternating between two streams with two workspaces
     (kernel timing on, events on each pass's stream), all passes on one
-    stream, and one pass over every cell must give the same bits."""
+    stream, and one pass over every cell must give the same bits: periodic
+    boxes, the N = 32 channel whose expansion hands most cells to the
+    full-layout launch (per-workspace hand-off lists), and a jittered mesh
+    (oblique-face expansion and its per-workspace lists)."""
     c = tk.Context(0)
     try:
-        m, cfg, m0 = box_case(8, N=16, precision=precision)
+        m, cfg, m0 = TWO_STREAM_CASES[case]()
         mesh = tk.Mesh(c, m)
         out = []
-        for chunk, two in ((None, True), (100, True), (100, False)):  # 6 passes, the last ragged
+        for chunk, two in ((None, True), (37, True), (37, False)):  # several passes, the last ragged
             st = tk.State(c, mesh, cfg, m0)
             assert st.streams(two)
             st.set_chunk(chunk or st.chunk()[1])
             c.prof_enable(True)
             st.step(3)
             c.prof_enable(False)
-            out.append((st.moments(), st.ranks()[0], st.export(77, cfg["N"])))
+            out.append((st.moments(), st.ranks()[0], st.export(77 % m["n_cells"], cfg["N"])))
             st.close()
         ma, ra, (ga, ua) = out[0]
         for mb, rb, (gb, ub) in out[1:]:
