@@ -147,38 +147,50 @@ def window_rows(rows, window, tail=0):
 
 
 def trace_summary(trace_csv, window, bench_json=None, tail=5):
-    """Markdown table of kernel-family times in the timed window of a
-    rocprofv3 --kernel-trace CSV, beside the HIP-event averages of the bench
-    line when given."""
+    """Markdown tables of kernel-family times of a rocprofv3 --kernel-trace
+    CSV of this script: the timed window (two streams), and the `tail`
+    per-kernel steps after it (one stream) beside the HIP-event times of the
+    bench line, launch by launch the same kernels."""
     import csv
     rows = []
     with open(trace_csv) as fh:
         for r in csv.DictReader(fh):
             rows.append({"name": r["Kernel_Name"], "start": int(r["Start_Timestamp"]),
                          "end": int(r["End_Timestamp"])})
-    win = window_rows(rows, window, tail)
-    fam = {}
-    for r in win:
-        f = family_of(r["name"])
-        if f:
-            t = fam.setdefault(f, [0.0, 0])
-            t[0] += (r["end"] - r["start"]) / 1e6
-            t[1] += 1
-    hip = {}
+    def families(win):
+        fam = {}
+        for r in win:
+            f = family_of(r["name"])
+            if f:
+                t = fam.setdefault(f, [0.0, 0])
+                t[0] += (r["end"] - r["start"]) / 1e6
+                t[1] += 1
+        return fam
+    hip, hip_launch = {}, {}
     if bench_json:
         with open(bench_json) as fh:
             b = json.loads(fh.read().strip().splitlines()[-1])
         for f, ms in b.get("kernel_ms_per_step_one_stream", b.get("kernel_ms_per_step", {})).items():
             hip[f] = ms
-    out = ["| family | launches | total (ms) | per step (ms) | average per launch (ms) | HIP events, per step (ms) |",
-           "|---|---|---|---|---|---|"]
-    for f, (ms, n) in sorted(fam.items(), key=lambda kv: -kv[1][0]):
-        he = f"{hip[f]:.3f}" if f in hip else "-"
-        out.append(f"| {f} | {n} | {ms:.2f} | {ms / window:.3f} | {ms / n:.4f} | {he} |")
+        roof = b.get("roofline") or {}
+        if roof.get("kernel"):
+            hip_launch[roof["kernel"]] = roof.get("avg_launch_ms")
+    win = window_rows(rows, window, tail)
+    out = [f"Timed window (the {window} steps, two streams):", "",
+           "| family | launches | total (ms) | per step (ms) | average per launch (ms) |", "|---|---|---|---|---|"]
+    for f, (ms, n) in sorted(families(win).items(), key=lambda kv: -kv[1][0]):
+        out.append(f"| {f} | {n} | {ms:.2f} | {ms / window:.3f} | {ms / n:.4f} |")
     span = (win[-1]["end"] - win[0]["start"]) / 1e6
-    out.append("")
-    out.append(f"Window: the last {window} steps, {len(win)} launches over {span:.1f} ms "
-               f"({span / window:.2f} ms per step of device time span).")
+    out += ["", f"{len(win)} launches over {span:.1f} ms ({span / window:.2f} ms per step of device time span).", ""]
+    if tail:
+        pw = window_rows(rows, tail, 0)
+        out += [f"Per-kernel window (the {tail} steps after it, one stream) against the bench line's HIP events:", "",
+                "| family | launches | per step (ms) | average per launch (ms) | HIP events, per step (ms) | "
+                "HIP events, average per launch (ms) |", "|---|---|---|---|---|---|"]
+        for f, (ms, n) in sorted(families(pw).items(), key=lambda kv: -kv[1][0]):
+            he = f"{hip[f]:.3f}" if f in hip else "-"
+            hl = f"{hip_launch[f]:.4f}" if hip_launch.get(f) else "-"
+            out.append(f"| {f} | {n} | {ms / tail:.3f} | {ms / n:.4f} | {he} | {hl} |")
     return "\n".join(out)
 
 

@@ -56,8 +56,7 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
                                                      int c0, double tol_o, int cap_o, int CS, double* fac_n,
                                                      int* rank_n, const double* Win, double* Wout, double* Wkeep,
                                                      double rel_thr, double abs_fac, double drop,
-                                                     double tail_frac, const int* cells, const int* cells_n,
-                                                     int* wvalid) {
+                                                     const int* cells, const int* cells_n, int* wvalid) {
   constexpr int NT = kEigThreads;
   constexpr int LD = N + 1;
   constexpr int NH = N / 2;
@@ -123,10 +122,6 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
   // off-diagonal floor: abs_fac of the trace, but never above 1e-4 of the
   // truncation budget (a pair that small cannot move energy across the cut)
   const double abs_thr = thr > 0.0 ? fmin(abs_fac * fabs(tot), 1e-4 * thr) : abs_fac * fabs(tot);
-  // directions whose Rayleigh quotient is below tail_frac of the budget (at
-  // most N of them, together below the budget when tail_frac <= 1/N) are
-  // always discarded: rotations between two of them are skipped
-  const double tail = (drop == 0.0 && thr > 0.0) ? tail_frac * thr : 0.0;
   if (wr) {
     // ---- full warm start: A <- V^T G V through Tm = G V --------------------
     for (int o = lane; o < N * N; o += NT) {
@@ -147,7 +142,7 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
     __syncthreads();
   }
   if (lane == 0) atomicAdd(&g_eig_stats[1], 1ull);
-  jacobi<NT, NH>(A, LD, V, LD, N, N, rel_thr, abs_thr, cs, sn, tt, pp, qq, flag, &s_conv, &g_eig_stats[2], tail);
+  jacobi<NT, NH>(A, LD, V, LD, N, N, rel_thr, abs_thr, cs, sn, tt, pp, qq, flag, &s_conv, &g_eig_stats[2]);
   sort_desc<NT>(A, LD + 1, N, order);
   if (wk) {
     for (int o = lane; o < N * N; o += NT) {
@@ -239,12 +234,11 @@ __global__ void k_identity_basis(int N, size_t count, double* W) {
 hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
                       double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
                       const double* Win, double* Wout, double* Wkeep, double rel_thr, double abs_fac,
-                      hipStream_t s, double drop, double tail_frac, const int* cells,
-                      const int* cells_n, int* wvalid) {
+                      hipStream_t s, double drop, const int* cells, const int* cells_n, int* wvalid) {
   if (count <= 0) return hipSuccess;
   dim3 grid(3 * count), blk(kEigThreads);
 #define TK_EIG(NN) hipLaunchKernelGGL(k_eig<NN>, grid, blk, 0, s, G, inst, ip, c0, tol_override, cap_override, CS, \
-                                      fac_n, rank_n, Win, Wout, Wkeep, rel_thr, abs_fac, drop, tail_frac, \
+                                      fac_n, rank_n, Win, Wout, Wkeep, rel_thr, abs_fac, drop, \
                                       cells, cells_n, wvalid)
   switch (N) {
     case 16: TK_EIG(16); break;

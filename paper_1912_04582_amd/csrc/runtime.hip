@@ -820,19 +820,17 @@ static tk_status state_step_once(tk_state* st) {
       // warm start from the kept basis over the full matrix (no leading-block
       // shortcut: accepting a block whose complement carries up to 1e-3 of
       // the truncation budget moved the end-of-run macroparameters by 4e-4
-      // against the FP64 path on the channel, against 4.6e-5 without it);
-      // pairs of directions below 1e-3 of the budget, all of them discarded
-      // and inside the FP32 noise of the expanded tensor, are not rotated
+      // against the FP64 path on the channel, against 4.6e-5 without it)
       e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
-                     nullptr, st->Wkeep, 1e-12, 1e-15, sq, 0.0, 1e-3, d.cells, d.cells_n, st->d_wvalid);
+                     nullptr, st->Wkeep, 1e-12, 1e-15, sq, 0.0, d.cells, d.cells_n, st->d_wvalid);
     } else {
       // FP64 path: first basis, Gram of the rotated unfoldings, final basis
       e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr, Wb,
-                     st->Wkeep, 1e-15, 1e-18, sq, 0.0, 0.0, d.cells, d.cells_n, st->d_wvalid);
+                     st->Wkeep, 1e-15, 1e-18, sq, 0.0, d.cells, d.cells_n, st->d_wvalid);
       if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, X, 0, Wb, G, sq, c0, d.cells_n);
       if (e == hipSuccess)
         e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, Wb, nullptr,
-                       nullptr, 1e-15, 1e-18, sq, 0.0, 0.0, d.cells, d.cells_n, nullptr);
+                       nullptr, 1e-15, 1e-18, sq, 0.0, d.cells, d.cells_n, nullptr);
     }
     prof_end(ctx, KID_EIG, ev, sq);
     if (e != hipSuccess) return fail("eig");
@@ -1055,11 +1053,9 @@ static tk_status state_lu_iteration(tk_state* st) {
   LuArgs lu{st->d_df_core, st->d_df_fac, st->d_df_rank, st->d_lu_col, 0, st->d_lu_dinv};
   double* X = (double*)st->X;
   // one stage over the listed cells (cells == nullptr: every cell), rounded
-  // into (fac_o, rank_o, core_o); the commit's eigensolves start from the
-  // state's kept bases (f + df is close to f) and keep the new ones
+  // into (fac_o, rank_o, core_o)
   auto stage = [&](int kind, int count, const int* cells, const int* cells_n, double* fac_o, int* rank_o,
                    double* core_o) -> tk_status {
-    const bool warm = kind == LU_COMMIT;
     DevState ds = d;
     ds.cells = cells;
     ds.cells_n = cells_n;
@@ -1075,12 +1071,11 @@ static tk_status state_lu_iteration(tk_state* st) {
       if (e != hipSuccess) return ctx_hip(ctx, e, "gram");
       prof_begin(ctx, KID_EIG, &ev);
       e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, fac_o, rank_o, nullptr, st->Wb,
-                     warm ? st->Wkeep : nullptr, 1e-15, 1e-18, q, 0.0, 0.0, cells, cells_n,
-                     warm ? st->d_wvalid : nullptr);
+                     nullptr, 1e-15, 1e-18, q, 0.0, cells, cells_n, nullptr);
       if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, X, 0, st->Wb, st->G, q, c0, cells_n);
       if (e == hipSuccess)
         e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, fac_o, rank_o, st->Wb, nullptr,
-                       nullptr, 1e-15, 1e-18, q, 0.0, 0.0, cells, cells_n, nullptr);
+                       nullptr, 1e-15, 1e-18, q, 0.0, cells, cells_n, nullptr);
       prof_end(ctx, KID_EIG, ev);
       if (e != hipSuccess) return ctx_hip(ctx, e, "eig");
       prof_begin(ctx, KID_PROJECT, &ev);

@@ -109,8 +109,8 @@ hipError_t launch_gram(int N, int count, const void* X, int mixed, double* G, hi
 hipError_t launch_eig(int N, int count, const double* G, const int* inst, const InstParams* ip, int c0,
                       double tol_override, int cap_override, int CS, double* fac_n, int* rank_n,
                       const double* Win, double* Wout, double* Wkeep, double rel_thr, double abs_fac,
-                      hipStream_t s, double drop = 0.0, double tail_frac = 0.0,
-                      const int* cells = nullptr, const int* cells_n = nullptr, int* wvalid = nullptr);
+                      hipStream_t s, double drop = 0.0, const int* cells = nullptr, const int* cells_n = nullptr,
+                      int* wvalid = nullptr);
 hipError_t eig_stats(unsigned long long* out, bool reset);
 // |xi . e| on the full grid for `count` unit normals (FP64), for the estimate
 hipError_t launch_absxi(int N, int count, const double* normals, double xi_min, double dxi, double* X,

@@ -18,17 +18,14 @@ namespace {
 // lda; n even), rotations accumulated into the columns of V (nv rows,
 // leading dimension ldv).  Round-robin ordering: n/2 disjoint pairs per
 // round, n-1 rounds per sweep; a pair rotates when |a_pq| exceeds both
-// rel_thr sqrt(|a_pp a_qq|) and abs_thr and one of a_pp, a_qq exceeds
-// `tail` (pairs of two directions below `tail` are left coupled: with tail at
-// most 1/n of the truncation budget every such direction is discarded by the
-// rank rule, which reads only their diagonal sum, the trace of that block).
-// Convergence is checked by a parallel scan of the off-diagonal elements
-// before each sweep; `sweeps` (nullable) counts the sweeps run, which are
-// also returned.  All threads of the block call it.
+// rel_thr sqrt(|a_pp a_qq|) and abs_thr.  Convergence is checked by a
+// parallel scan of the off-diagonal elements before each sweep; `sweeps`
+// (nullable) counts the sweeps run, which are also returned.  All threads of
+// the block call it.
 template <int NT, int NHMAX>
 __device__ int jacobi(double* A, int lda, double* V, int ldv, int nv, int n, double rel_thr, double abs_thr,
                        double* cs, double* sn, double* tt, int* pp, int* qq, int* flag, int* conv,
-                       unsigned long long* sweeps, double tail = 0.0) {
+                       unsigned long long* sweeps) {
   // the (I, J) pair blocks of the update, tabulated once per call
   __shared__ unsigned char b_i[NHMAX * (NHMAX + 1) / 2], b_j[NHMAX * (NHMAX + 1) / 2];
   const int lane = threadIdx.x;
@@ -51,8 +48,8 @@ __device__ int jacobi(double* A, int lda, double* V, int ldv, int nv, int n, dou
     for (int o = lane; o < n * n; o += NT) {
       const int i = o / n, j = o % n;
       if (j <= i) continue;
-      const double apq = A[i * lda + j], aii = A[i * lda + i], ajj = A[j * lda + j];
-      if (fabs(apq) > fmax(rel_thr * sqrt(fabs(aii * ajj)), abs_thr) && fmax(aii, ajj) > tail) *conv = 0;
+      const double apq = A[i * lda + j];
+      if (fabs(apq) > fmax(rel_thr * sqrt(fabs(A[i * lda + i] * A[j * lda + j])), abs_thr)) *conv = 0;
     }
     __syncthreads();
     if (*conv) break;
@@ -80,7 +77,7 @@ __device__ int jacobi(double* A, int lda, double* V, int ldv, int nv, int n, dou
         if (p > q) { const int t = p; p = q; q = t; }
         const double app = A[p * lda + p], aqq = A[q * lda + q], apq = A[p * lda + q];
         double c = 1.0, s = 0.0, t = 0.0;
-        if (fabs(apq) > fmax(rel_thr * sqrt(fabs(app * aqq)), abs_thr) && fmax(app, aqq) > tail && apq != 0.0) {
+        if (fabs(apq) > fmax(rel_thr * sqrt(fabs(app * aqq)), abs_thr) && apq != 0.0) {
           const double th = (aqq - app) / (2.0 * apq);
           if (fabs(th) > 1e150) {
             t = 0.5 / th;
