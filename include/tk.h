@@ -357,26 +357,29 @@ typedef struct {
 /* Continuous batching of independent solves over one device.  A worker
  * thread admits queued requests in arrival order among those whose
  * estimated device memory fits what the running ones leave of hbm_budget
- * (0: the context's budget).  The requests admitted together that share N,
- * precision and whether their mesh has faces off the coordinate axes form
- * a cohort: the instances of one resident batched state
- * with its own stream, so one step of the cohort is one set of launches
- * over all their cells.  Each cohort keeps one step in flight and starts
- * its next as soon as that one completes, without waiting for the other
- * cohorts.  A request retires when its residual (tk_state_step) falls
- * below residual_tol, at max_steps, or with TK_ENUMERIC when one of its
- * cells turns non-positive or non-finite; its cells are then no longer
- * stepped, and the cohort's memory returns to the budget when its last
- * request retires (requests never join a running cohort).  A request's
- * result does not depend on the requests served beside it.               */
+ * (0: the context's budget).  Requests that share N, precision and
+ * whether their mesh has faces off the coordinate axes form a cohort: the
+ * instances of one resident batched state with its own stream, so one step
+ * of the cohort is one set of launches over all their cells.  A newly
+ * admitted request joins the running cohort of its kind at that cohort's
+ * next step boundary (the cohort's state is rebuilt with the running
+ * requests' states copied over on the device; old and new states coexist
+ * for the rebuild), or forms a new cohort when none runs.  Each cohort
+ * keeps one step in flight and starts its next as soon as that one
+ * completes, without waiting for the other cohorts.  A request retires when
+ * its residual (tk_step) falls below residual_tol, at max_steps, or with
+ * TK_ENUMERIC when one of its cells turns non-positive or non-finite; its
+ * cells are then no longer stepped, and its memory returns to the budget
+ * when its cohort ends or is rebuilt.  A request's result does not depend
+ * on the requests served beside it.                                       */
 tk_status tk_serve_create(tk_ctx* ctx, size_t hbm_budget, tk_server** out);
 /* Never blocks; TK_ENOMEM only for a request that could never fit.       */
 tk_status tk_serve_submit(tk_server* srv, const tk_request* req, uint64_t* ticket);
 /* Returns the request's status (TK_PENDING while queued or running) and
  * fills *res; TK_ENOTFOUND for an unknown ticket.                         */
 tk_status tk_serve_poll(tk_server* srv, uint64_t ticket, tk_result* res);
-/* out4[0] cohorts formed, [1] cohort steps (shared launch sets), [2]
- * request steps, [3] requests in the largest cohort.                      */
+/* out4[0] cohorts formed or rebuilt, [1] cohort steps (shared launch
+ * sets), [2] request steps, [3] requests in the largest cohort.           */
 tk_status tk_serve_stats(tk_server* srv, int64_t* out4);
 /* Stops the worker (running requests stay TK_PENDING) and frees all.     */
 tk_status tk_serve_destroy(tk_server* srv);

@@ -388,6 +388,9 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     nc += meshes[k]->n_cells;
     nbc += (int)meshes[k]->bc.size();
   }
+  // a server's states share one layout, so that instances can move between
+  // them (state_copy_instance)
+  if (served) CS = kMaxCap;
   std::unique_ptr<tk_state> st(new tk_state());
   st->ctx = ctx;
   st->N = N;
@@ -1143,6 +1146,33 @@ tk_status state_create_served(tk_ctx* ctx, int count, const tk_mesh* const* mesh
   if (!ctx) return TK_EINVAL;
   std::lock_guard<std::recursive_mutex> g(ctx->mu);
   return state_create(ctx, count, meshes, params, macros, false, out, true);
+}
+
+// Copies the current Tucker state of instance ks of src (its cells' cores,
+// factors and ranks, and the kept eigenbases with their validity) over
+// instance kd of dst: the same mesh and parameters, N, precision and layout
+// (CS).  Enqueued on dst's context stream after src's pending work; dst then
+// continues that instance exactly where src left it.
+tk_status state_copy_instance(tk_state* dst, int kd, tk_state* src, int ks) {
+  if (!dst || !src || kd < 0 || kd >= dst->ninst || ks < 0 || ks >= src->ninst || dst->plain || src->plain)
+    return TK_EINVAL;
+  const int n = src->inst_off[ks + 1] - src->inst_off[ks];
+  if (n != dst->inst_off[kd + 1] - dst->inst_off[kd] || dst->N != src->N || dst->CS != src->CS ||
+      dst->mixed != src->mixed)
+    return ctx_fail(dst->ctx, TK_EINVAL, "copy instance: different shapes");
+  const size_t a = (size_t)src->inst_off[ks], b = (size_t)dst->inst_off[kd];
+  const size_t N = dst->N, CS = dst->CS;
+  hipStream_t q = dst->ctx->stream;
+  hipError_t e = hipStreamSynchronize(src->ctx->stream);
+  auto cp = [&](void* d, const void* s, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(d, s, bytes, hipMemcpyDeviceToDevice, q);
+  };
+  cp(dst->core[dst->cur] + b * CS * CS * CS, src->core[src->cur] + a * CS * CS * CS, sizeof(double) * n * CS * CS * CS);
+  cp(dst->fac[dst->cur] + b * 3 * CS * N, src->fac[src->cur] + a * 3 * CS * N, sizeof(double) * n * 3 * CS * N);
+  cp(dst->rank[dst->cur] + b * 3, src->rank[src->cur] + a * 3, sizeof(int) * n * 3);
+  cp(dst->Wkeep + b * 3 * N * N, src->Wkeep + a * 3 * N * N, sizeof(double) * n * 3 * N * N);
+  cp(dst->d_wvalid + b * 3, src->d_wvalid + a * 3, sizeof(int) * n * 3);
+  return ctx_hip(dst->ctx, e, "copy instance");
 }
 
 // Stops stepping instance k of a state from the next step on (enqueued on

@@ -1,14 +1,18 @@
 // Serving: continuous batching of independent solves on one device.
 //
-// Requests admitted together that share N, precision and whether their
-// mesh has faces off the coordinate axes (which selects the expansion
-// kernels) become the instances of one batched state (a cohort), so a step
-// of a cohort is one set of launches over the cells of all its requests.  A worker thread
+// Requests that share N, precision and whether their mesh has faces off the
+// coordinate axes (which selects the expansion kernels) are the instances of
+// one batched state (a cohort), so a step of a cohort is one set of launches
+// over the cells of all its requests.  A worker thread
 //   1. admits queued requests, in arrival order among those that fit,
 //      whenever their estimated device memory fits what the running cohorts
 //      leave of the budget (a request that could never fit is refused at
-//      submit), and forms cohorts of them, each with its own sub-context,
-//      default-priority stream and state;
+//      submit).  Admitted requests join the cohort of their kind at its next
+//      step boundary: the cohort is rebuilt with its running requests and
+//      the new ones, the running ones' Tucker states and kept eigenbases
+//      copied over device to device, so they continue exactly where they
+//      were.  With no cohort of their kind they form a new one (own
+//      sub-context, default-priority stream and state);
 //   2. keeps one step in flight per cohort, with the residual and the numeric
 //      flag of every instance copied back; a cohort whose step has completed
 //      gets its next step at once, without waiting for the other cohorts;
@@ -16,7 +20,8 @@
 //      reached its step limit, or whose cells turned non-finite: its
 //      macroparameters are copied out and its instance is frozen (moments
 //      and rounding skip its cells from the next step on).  A cohort's
-//      memory returns to the budget when its last request retires.
+//      memory returns to the budget when its last request retires or when
+//      it is rebuilt (during a rebuild the old and new states coexist).
 // Instances never exchange data and every kernel's arithmetic on a cell is
 // the same whichever cells share its launch, so a request's result does not
 // depend on the requests served beside it.
@@ -82,6 +87,7 @@ struct tk_server {
   std::map<uint64_t, std::unique_ptr<ServeReq>> reqs;
   std::deque<uint64_t> queue;
   std::vector<std::unique_ptr<Cohort>> cohorts;  // worker thread only
+  std::vector<ServeReq*> pending;  // admitted, waiting for a running cohort of their kind
   int64_t stats[4] = {0, 0, 0, 0};  // cohorts, cohort steps, request steps, largest cohort
   std::chrono::steady_clock::time_point t0;
   double now() const {
@@ -131,6 +137,12 @@ tk_status form(int device, Cohort* c) {
   c->live.assign(n, 1);
   c->n_live = n;
   return s;
+}
+
+// Requests that can share a batched state: the same N and precision, and
+// the same face kind (which selects the expansion kernels).
+bool same_kind(const ServeReq* a, const ServeReq* b) {
+  return a->params.N == b->params.N && a->params.precision == b->params.precision && a->oblique == b->oblique;
 }
 
 struct Out {
@@ -210,33 +222,75 @@ void worker_loop(tk_server* srv) {
       r->t_admit = srv->now();
       adm.push_back(r);
     }
-    if (!adm.empty()) {
+    srv->pending.insert(srv->pending.end(), adm.begin(), adm.end());
+    if (!srv->pending.empty()) {
       lk.unlock();
-      std::vector<std::unique_ptr<Cohort>> made, failed;
-      for (ServeReq* r : adm) {
-        Cohort* c = nullptr;
-        for (auto& m : made)
-          if (m->mem[0]->params.N == r->params.N && m->mem[0]->params.precision == r->params.precision &&
-              m->mem[0]->oblique == r->oblique)
-            c = m.get();
-        if (!c) {
-          made.emplace_back(new Cohort());
-          c = made.back().get();
+      // one group per kind, in arrival order
+      std::vector<std::vector<ServeReq*>> groups;
+      for (ServeReq* r : srv->pending) {
+        std::vector<ServeReq*>* g = nullptr;
+        for (auto& x : groups)
+          if (same_kind(x[0], r)) g = &x;
+        if (!g) {
+          groups.emplace_back();
+          g = &groups.back();
         }
-        c->mem.push_back(r);
+        g->push_back(r);
       }
-      for (auto it = made.begin(); it != made.end();) {
-        const tk_status s = form(srv->parent->device, it->get());
-        if (s == TK_OK) {
-          ++it;
+      std::vector<ServeReq*> waiting;
+      std::vector<std::unique_ptr<Cohort>> made, failed;
+      std::vector<std::pair<Cohort*, std::unique_ptr<Cohort>>> merged;  // old cohort, its replacement
+      for (auto& g : groups) {
+        Cohort* idle = nullptr;
+        bool busy = false;
+        for (auto& c : srv->cohorts) {
+          if (!same_kind(c->mem[0], g[0]) || c->n_live == 0 || c->step_status != TK_OK) continue;
+          if (c->inflight) busy = true;
+          else if (!idle) idle = c.get();
+        }
+        if (!idle && busy) {
+          // join a running cohort of this kind when its step completes
+          waiting.insert(waiting.end(), g.begin(), g.end());
           continue;
         }
-        release(it->get());
-        (*it)->step_status = s;
-        failed.push_back(std::move(*it));
-        it = made.erase(it);
+        std::unique_ptr<Cohort> c(new Cohort());
+        std::vector<int> from;  // instance of the old cohort each migrated request had
+        if (idle)
+          for (size_t k = 0; k < idle->mem.size(); ++k)
+            if (idle->live[k]) {
+              c->mem.push_back(idle->mem[k]);
+              from.push_back((int)k);
+            }
+        c->mem.insert(c->mem.end(), g.begin(), g.end());
+        tk_status s = form(srv->parent->device, c.get());
+        for (size_t k = 0; k < from.size() && s == TK_OK; ++k)
+          s = state_copy_instance(c->st, (int)k, idle->st, from[k]);
+        if (s == TK_OK && !from.empty() && hipStreamSynchronize(c->ctx->stream) != hipSuccess) s = TK_EDEVICE;
+        if (s == TK_OK) {
+          if (idle) merged.emplace_back(idle, std::move(c));
+          else made.push_back(std::move(c));
+          continue;
+        }
+        release(c.get());
+        if (idle) {
+          // the running requests stay where they were; the new ones alone
+          std::unique_ptr<Cohort> a(new Cohort());
+          a->mem = g;
+          s = form(srv->parent->device, a.get());
+          if (s == TK_OK) {
+            made.push_back(std::move(a));
+            continue;
+          }
+          release(a.get());
+          c.reset(new Cohort());
+          c->mem = g;
+        }
+        c->step_status = s;
+        failed.push_back(std::move(c));
       }
+      std::vector<std::unique_ptr<Cohort>> old;
       lk.lock();
+      srv->pending = waiting;
       const double t = srv->now();
       for (auto& c : failed)
         for (ServeReq* r : c->mem) {
@@ -244,10 +298,30 @@ void worker_loop(tk_server* srv) {
           r->t_done = t;
           srv->in_use -= r->bytes;
         }
+      for (auto& m : merged) {
+        // the replaced cohort's retired requests' memory returns to the budget
+        size_t live = 0;
+        for (size_t k = 0; k < m.first->mem.size(); ++k)
+          if (m.first->live[k]) live += m.first->mem[k]->bytes;
+        srv->in_use -= m.first->bytes - live;
+        for (auto& c : srv->cohorts)
+          if (c.get() == m.first) {
+            old.push_back(std::move(c));
+            c = std::move(m.second);
+            srv->stats[0] += 1;
+            srv->stats[3] = std::max<int64_t>(srv->stats[3], (int64_t)c->mem.size());
+            break;
+          }
+      }
       for (auto& c : made) {
         srv->stats[0] += 1;
         srv->stats[3] = std::max<int64_t>(srv->stats[3], (int64_t)c->mem.size());
         srv->cohorts.push_back(std::move(c));
+      }
+      if (!old.empty()) {
+        lk.unlock();
+        for (auto& c : old) release(c.get());
+        lk.lock();
       }
     }
     if (srv->cohorts.empty()) {

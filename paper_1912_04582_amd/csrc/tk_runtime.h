@@ -172,3 +172,4 @@ tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag);
 tk_status state_create_served(tk_ctx* ctx, int count, const tk_mesh* const* meshes, const tk_params* params,
                               const double* const* macros, tk_state** out);
 tk_status state_freeze_instance(tk_state* st, int k);
+tk_status state_copy_instance(tk_state* dst, int kd, tk_state* src, int ks);

@@ -382,6 +382,50 @@ def test_serving_alone_equals_mix(ctx):
     st.close(); mesh.close()
 
 
+def test_serving_late_request_joins_the_running_cohort(ctx):
+    """A request admitted while another of its kind runs joins that cohort
+    at its next step boundary (the cohort's state rebuilt, the running
+    request's state copied over on the device); both results equal the
+    requests served alone, bit for bit, and the late steps are shared."""
+    import time
+    reqs = []
+    for k, (n, cap, tol) in enumerate([(4, 6, 1e-6), (3, 4, 1e-5)]):
+        m = synth.periodic_box(n, length=0.5 + 0.1 * k)
+        cfg = dict(N=16, xi_max=4.5, cap=cap, tol=tol, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=0.2, Rg=0.5, m=1.0,
+                   seed=70 + k, init="random", precision="mixed")
+        reqs.append((m, cfg, synth.initial_macros(cfg, m)))
+    steps = (200, 12)
+
+    def wait(srv, t):
+        t0 = time.time()
+        while time.time() - t0 < 120:
+            r = srv.poll(t)
+            if r["status"] != tk.TK_PENDING:
+                return r
+            time.sleep(0.005)
+        raise TimeoutError
+
+    srv = tk.Server(ctx)
+    ta = srv.submit(*reqs[0], steps[0], 1e-12)
+    t0 = time.time()
+    while srv.poll(ta, want_macros=False)["steps"] < 3 and time.time() - t0 < 60:
+        time.sleep(0.001)
+    assert srv.poll(ta, want_macros=False)["status"] == tk.TK_PENDING
+    tb = srv.submit(*reqs[1], steps[1], 1e-12)
+    rb, ra = wait(srv, tb), wait(srv, ta)
+    stats = srv.stats()
+    srv.close()
+    assert ra["status"] == rb["status"] == tk.TK_OK and ra["steps"] == steps[0] and rb["steps"] == steps[1]
+    assert stats["cohorts"] == 2 and stats["largest_cohort"] == 2, stats
+    assert stats["request_steps"] == sum(steps) and stats["cohort_steps"] == steps[0], stats
+    for item, n, got in zip(reqs, steps, (ra, rb)):
+        alone = tk.Server(ctx)
+        t = alone.submit(*item, n, 1e-12)
+        r = wait(alone, t)
+        alone.close()
+        assert np.array_equal(got["macros"], r["macros"])
+
+
 def test_serving_refuses_requests_that_never_fit(ctx):
     srv = tk.Server(ctx, budget=1 << 20)
     m = synth.periodic_box(3)
