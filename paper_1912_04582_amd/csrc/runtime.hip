@@ -371,7 +371,8 @@ size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk) {
 }
 
 static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* meshes, const tk_params* params,
-                              const double* const* macros, bool plain, tk_state** out, bool served = false) {
+                              const double* const* macros, bool plain, tk_state** out, bool served = false,
+                              int est_skip = 0) {
   if (!ctx || !out || count <= 0 || !meshes || !params || !macros) return ctx_fail(ctx, TK_EINVAL, "state: null argument");
   *out = nullptr;
   if (ctx->device < 0) return ctx_fail(ctx, TK_EDEVICE, "state: host-only context");
@@ -414,9 +415,11 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
   bool oblique = false;
   for (int k = 0; k < count; ++k) oblique |= meshes[k]->oblique;
   st->inst_off.assign(count + 1, 0);
+  st->est_off.assign(count + 1, 0);
   int c0 = 0, b0 = 0;
   for (int k = 0; k < count; ++k) {
     const tk_mesh* m = meshes[k];
+    const int est_start = (int)est_inst.size();
     const tk_params& p = params[k];
     const double dxi = 2.0 * p.xi_max / (N - 1);
     // time step of this instance
@@ -491,9 +494,11 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
         }
     }
     st->inst_off[k] = c0;
+    st->est_off[k] = est_start;
     c0 += m->n_cells;
     b0 += (int)m->bc.size();
   }
+  st->est_off[count] = (int)est_inst.size();
   st->inst_off[count] = c0;
   st->ip_host = ip;
   // chunk of cells processed per rounding pass
@@ -635,7 +640,7 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     if (e == hipSuccess) e = launch_identity_basis(N, (size_t)nc * 3, S->Wkeep, q);
     if (e == hipSuccess) e = launch_fill_int(S->d_wvalid, (size_t)nc * 3, 1, q);
     if (e == hipSuccess) e = hipMemsetAsync(S->d_rstats, 0, 8 * sizeof(unsigned long long), q);
-    if (e == hipSuccess && oblique && n_est > 0) {
+    if (e == hipSuccess && oblique && n_est > st->est_off[std::min(est_skip, count)]) {
       // |xi . e| estimate of every oblique face: truncated HOSVD of the exact
       // tensor, mode ranks <= kEstCap, singular values <= kEstDrop sigma_1 dropped
       const size_t per_face = (size_t)N * N * N * 8 + 3 * (size_t)N * N * 8;
@@ -651,7 +656,9 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
         return s2;
       }
       e = hipMemcpyAsync(d_nrm, est_nrm.data(), sizeof(double) * est_nrm.size(), hipMemcpyHostToDevice, q);
-      int f0 = 0;
+      // the estimates of the first est_skip instances are copied in by the
+      // caller (state_copy_instance)
+      int f0 = st->est_off[std::min(est_skip, count)];
       while (f0 < n_est && e == hipSuccess) {
         const int cnt = std::min(fch, n_est - f0);
         // every instance of a state shares N; the velocity grid is per instance:
@@ -1142,17 +1149,18 @@ tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait, boo
 // host memory (h_res[n_instances], h_flag[n_instances]); the caller
 // synchronises the stream.
 tk_status state_create_served(tk_ctx* ctx, int count, const tk_mesh* const* meshes, const tk_params* params,
-                              const double* const* macros, tk_state** out) {
+                              const double* const* macros, tk_state** out, int est_skip) {
   if (!ctx) return TK_EINVAL;
   std::lock_guard<std::recursive_mutex> g(ctx->mu);
-  return state_create(ctx, count, meshes, params, macros, false, out, true);
+  return state_create(ctx, count, meshes, params, macros, false, out, true, est_skip);
 }
 
 // Copies the current Tucker state of instance ks of src (its cells' cores,
-// factors and ranks, and the kept eigenbases with their validity) over
-// instance kd of dst: the same mesh and parameters, N, precision and layout
-// (CS).  Enqueued on dst's context stream after src's pending work; dst then
-// continues that instance exactly where src left it.
+// factors and ranks, the kept eigenbases with their validity, and the
+// |xi . e| estimates of its oblique faces) over instance kd of dst: the same
+// mesh and parameters, N, precision and layout (CS).  Enqueued on dst's
+// context stream after src's pending work; dst then continues that instance
+// exactly where src left it.
 tk_status state_copy_instance(tk_state* dst, int kd, tk_state* src, int ks) {
   if (!dst || !src || kd < 0 || kd >= dst->ninst || ks < 0 || ks >= src->ninst || dst->plain || src->plain)
     return TK_EINVAL;
@@ -1172,6 +1180,15 @@ tk_status state_copy_instance(tk_state* dst, int kd, tk_state* src, int ks) {
   cp(dst->rank[dst->cur] + b * 3, src->rank[src->cur] + a * 3, sizeof(int) * n * 3);
   cp(dst->Wkeep + b * 3 * N * N, src->Wkeep + a * 3 * N * N, sizeof(double) * n * 3 * N * N);
   cp(dst->d_wvalid + b * 3, src->d_wvalid + a * 3, sizeof(int) * n * 3);
+  const int ne = src->est_off[ks + 1] - src->est_off[ks];
+  if (ne != dst->est_off[kd + 1] - dst->est_off[kd]) return ctx_fail(dst->ctx, TK_EINVAL, "copy instance: faces differ");
+  if (ne > 0) {
+    const size_t ea = (size_t)src->est_off[ks], eb = (size_t)dst->est_off[kd];
+    const size_t E3 = (size_t)kEstCap * kEstCap * kEstCap, EF = 3 * (size_t)kEstCap * N;
+    cp(dst->d_est_core + eb * E3, src->d_est_core + ea * E3, sizeof(double) * ne * E3);
+    cp(dst->d_est_fac + eb * EF, src->d_est_fac + ea * EF, sizeof(double) * ne * EF);
+    cp(dst->d_est_rank + eb * 3, src->d_est_rank + ea * 3, sizeof(int) * ne * 3);
+  }
   return ctx_hip(dst->ctx, e, "copy instance");
 }
 

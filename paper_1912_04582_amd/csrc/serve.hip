@@ -112,7 +112,9 @@ void release(Cohort* c) {
   c->h_flag = nullptr;
 }
 
-tk_status form(int device, Cohort* c) {
+// migrated: the first requests of c->mem, whose states (and face
+// estimates) the caller copies in from their previous cohort
+tk_status form(int device, Cohort* c, int migrated = 0) {
   const int n = (int)c->mem.size();
   for (ServeReq* r : c->mem) c->bytes += r->bytes;
   tk_status s = tk_ctx_create(device, c->bytes + (256u << 20), nullptr, &c->ctx);
@@ -127,7 +129,7 @@ tk_status form(int device, Cohort* c) {
   }
   if (s == TK_OK)
     s = state_create_served(c->ctx, n, (const tk_mesh* const*)c->meshes.data(), params.data(), macros.data(),
-                            &c->st);
+                            &c->st, migrated);
   // one rounding pass per step (pass-size trials would serialise the mix)
   if (s == TK_OK) s = tk_state_set_chunk(c->st, c->st->chunk_max);
   if (s == TK_OK && (hipHostMalloc((void**)&c->h_res, sizeof(double) * n) != hipSuccess ||
@@ -262,7 +264,7 @@ void worker_loop(tk_server* srv) {
               from.push_back((int)k);
             }
         c->mem.insert(c->mem.end(), g.begin(), g.end());
-        tk_status s = form(srv->parent->device, c.get());
+        tk_status s = form(srv->parent->device, c.get(), (int)from.size());
         for (size_t k = 0; k < from.size() && s == TK_OK; ++k)
           s = state_copy_instance(c->st, (int)k, idle->st, from[k]);
         if (s == TK_OK && !from.empty() && hipStreamSynchronize(c->ctx->stream) != hipSuccess) s = TK_EDEVICE;

@@ -72,6 +72,7 @@ struct tk_state {
   std::vector<tk_params> params;
   std::vector<const tk_mesh*> meshes;
   std::vector<int> inst_off;
+  std::vector<int> est_off;  // first |xi . e| estimate of each instance (oblique faces, instance order)
   std::vector<tk::InstParams> ip_host;
   std::vector<void*> allocs;
   // device tables
@@ -169,7 +170,9 @@ tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait, boo
 size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk);
 void state_tune_begin(tk_state* st);
 tk_status state_step_residual_async(tk_state* st, double* h_res, int* h_flag);
+// est_skip: the |xi . e| estimates of the first est_skip instances are not
+// computed (state_copy_instance brings them from a state that has them)
 tk_status state_create_served(tk_ctx* ctx, int count, const tk_mesh* const* meshes, const tk_params* params,
-                              const double* const* macros, tk_state** out);
+                              const double* const* macros, tk_state** out, int est_skip = 0);
 tk_status state_freeze_instance(tk_state* st, int k);
 tk_status state_copy_instance(tk_state* dst, int kd, tk_state* src, int ks);

@@ -382,15 +382,20 @@ def test_serving_alone_equals_mix(ctx):
     st.close(); mesh.close()
 
 
-def test_serving_late_request_joins_the_running_cohort(ctx):
+@pytest.mark.parametrize("faces", ["axis", "oblique"])
+def test_serving_late_request_joins_the_running_cohort(ctx, faces):
     """A request admitted while another of its kind runs joins that cohort
     at its next step boundary (the cohort's state rebuilt, the running
-    request's state copied over on the device); both results equal the
-    requests served alone, bit for bit, and the late steps are shared."""
+    request's state, kept bases and face estimates copied over on the
+    device); both results equal the requests served alone, bit for bit, and
+    the late steps are shared."""
     import time
     reqs = []
     for k, (n, cap, tol) in enumerate([(4, 6, 1e-6), (3, 4, 1e-5)]):
-        m = synth.periodic_box(n, length=0.5 + 0.1 * k)
+        if faces == "axis":
+            m = synth.periodic_box(n, length=0.5 + 0.1 * k)
+        else:
+            m = synth.jittered_box(n, n, 3, 1.0 / n, seed=80 + k)
         cfg = dict(N=16, xi_max=4.5, cap=cap, tol=tol, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=0.2, Rg=0.5, m=1.0,
                    seed=70 + k, init="random", precision="mixed")
         reqs.append((m, cfg, synth.initial_macros(cfg, m)))
