@@ -581,13 +581,16 @@ def serve_run(reqs, rate, seed=5):
                 status=[r["status"] for r in res], steps=[r["steps"] for r in res])
 
 
-def run_serve(count, max_steps, seed=4):
-    log(f"serving {count} requests: saturated, then Poisson at 0.7x and 0.35x the saturated rate")
+def run_serve(count, max_steps, seed=4, rate=None):
     specs = synth.configs.serve_requests(seed=seed, count=count)
     reqs = []
     for c in specs:
         m = synth.configs.make_mesh(c)
         reqs.append((m, c, synth.initial_macros(c, m), min(max_steps, c["steps"]), c["residual_tol"]))
+    if rate:
+        log(f"serving {count} requests: Poisson at {rate} per second")
+        return dict(paced=serve_run(reqs, rate), rate=rate, cells=[q[0]["n_cells"] for q in reqs])
+    log(f"serving {count} requests: saturated, then Poisson at 0.7x and 0.35x the saturated rate")
     sat = serve_run(reqs, None)
     rate = 0.7 * count / sat["seconds"]
     paced = serve_run(reqs, rate)
@@ -656,6 +659,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-count", type=int, default=12)
     ap.add_argument("--serve-max-steps", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="only the Poisson run, at this many requests per second")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB read + 1 GiB write elementwise copy, five times (the "
                          "reference kernel for scaling HBM byte counters)")
@@ -695,13 +700,13 @@ def main():
         print(json.dumps({"error": "one GPU per process: the step runs on a single device; --gpus must be 1"}))
         sys.exit(2)
     if a.workload == "serve":
-        r = run_serve(a.serve_count, a.serve_max_steps)
+        r = run_serve(a.serve_count, a.serve_max_steps, rate=a.serve_rate)
         out = {"metric": "served Tucker S-model cell-updates/s; p50/p99 request latency",
                "unit": "cell-updates/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None, "dtype": "f32 terms + f64 rounding", "data": "synthetic",
                "config": {"workload": f"serving {a.serve_count} jittered-box requests",
                           "max_steps": a.serve_max_steps, "cells": r["cells"]}}
-        for key in ("saturated", "paced", "paced_half"):
+        for key in [k for k in ("saturated", "paced", "paced_half") if k in r]:
             q = r[key]
             out[key] = {"value": q["updates"] / q["seconds"], "seconds": q["seconds"],
                         "p50_latency_s": float(np.percentile(q["latency"], 50)),
@@ -711,7 +716,8 @@ def main():
             log(f"serve {key}: {out[key]['value']:.4g} cell-updates/s, p50 {out[key]['p50_latency_s']:.2f} s, "
                 f"p99 {out[key]['p99_latency_s']:.2f} s over {q['seconds']:.1f} s")
         out["arrival_rate_per_s"] = r["rate"]
-        out["arrival_rate_half_per_s"] = 0.5 * r["rate"]
+        if "paced_half" in r:
+            out["arrival_rate_half_per_s"] = 0.5 * r["rate"]
         out["value"] = out["paced"]["value"]
         print(json.dumps(out), flush=True)
         return
