@@ -4,12 +4,13 @@
 // One workgroup per N x N matrix runs cyclic Jacobi with the parallel
 // round-robin ordering (N/2 disjoint rotations per round, N-1 rounds per
 // sweep) in LDS, until no off-diagonal element exceeds both
-// rel_thr sqrt(|a_pp a_qq|) and abs_fac trace, the latter capped at 1e-4 of
+// rel_thr sqrt(|a_pp a_qq|) and abs_fac trace, the latter capped at 1e-2 of
 // the truncation budget (FP64 path 1e-15 and 1e-18; mixed path 1e-12 and
-// 1e-15: the FP32 term assembly leaves noise of about that size among the
-// smallest directions, all of them discarded, and rotating it is wasted
-// work).  The discarded energy is read from the diagonal of an orthonormal
-// rotation of G, so the error bound holds at any convergence level; the
+// 1e-13: the FP32 term assembly leaves noise among the smallest directions
+// whose couplings to the kept ones hover near a lower floor, so every step
+// re-rotated them for nothing).  The discarded energy is read from the
+// diagonal of an orthonormal rotation of G, so the error bound holds at any
+// convergence level; the
 // thresholds only decide how close to optimal the kept subspace is.
 // Eigenvalues of G_a are the
 // squared singular values of the mode-a unfolding (eq. svd).  The kept rank
@@ -119,9 +120,11 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
     for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
   }
   const double thr = tol * tol * tot / 3.0;
-  // off-diagonal floor: abs_fac of the trace, but never above 1e-4 of the
-  // truncation budget (a pair that small cannot move energy across the cut)
-  const double abs_thr = thr > 0.0 ? fmin(abs_fac * fabs(tot), 1e-4 * thr) : abs_fac * fabs(tot);
+  // off-diagonal floor: abs_fac of the trace, but never above 1e-2 of the
+  // truncation budget: a coupling that small moves at most its square over
+  // the eigenvalue gap across the cut (far below the budget), and turns the
+  // smallest kept directions by at most 1e-2 radian
+  const double abs_thr = thr > 0.0 ? fmin(abs_fac * fabs(tot), 1e-2 * thr) : abs_fac * fabs(tot);
   if (wr) {
     // ---- full warm start: A <- V^T G V through Tm = G V --------------------
     for (int o = lane; o < N * N; o += NT) {

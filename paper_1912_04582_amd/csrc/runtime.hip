@@ -832,7 +832,7 @@ static tk_status state_step_once(tk_state* st) {
       // the truncation budget moved the end-of-run macroparameters by 4e-4
       // against the FP64 path on the channel, against 4.6e-5 without it)
       e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr,
-                     nullptr, st->Wkeep, 1e-12, 1e-15, sq, 0.0, d.cells, d.cells_n, st->d_wvalid);
+                     nullptr, st->Wkeep, 1e-12, 1e-13, sq, 0.0, d.cells, d.cells_n, st->d_wvalid);
     } else {
       // FP64 path: first basis, Gram of the rotated unfoldings, final basis
       e = launch_eig(st->N, cnt, G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, d.fac_n, d.rank_n, nullptr, Wb,
