@@ -508,18 +508,21 @@ def run_batch(steps, warmup, count, prof_steps=3):
 
 
 def run_lusgs(cfg, mesh, m0, iters, cfl):
-    """LU-SGS iterations (FP64, CFL `cfl`) against explicit FP64 steps (the
-    workload's CFL) from the same initial state: time per iteration, the
-    kernel families of one more iteration, and the residual per iteration."""
+    """LU-SGS iterations (CFL `cfl`) against explicit steps (the workload's
+    CFL) from the same initial state, FP64 and mixed: time per iteration,
+    the kernel families of one more iteration, and the residual per
+    iteration."""
     c64 = dict(cfg, precision="fp64")
+    cmx = dict(cfg, precision="mixed")
     out = {}
     ctx = tk.Context(0)
     try:
         tm = tk.Mesh(ctx, mesh)
-        for kind, c in (("lusgs", dict(c64, cfl=cfl)), ("explicit", c64)):
+        for kind, c in (("lusgs", dict(c64, cfl=cfl)), ("explicit", c64), ("lusgs_mixed", dict(cmx, cfl=cfl)),
+                        ("explicit_mixed", cmx)):
             st = tk.State(ctx, tm, c, m0)
             st.streams(False)
-            go = st.lusgs if kind == "lusgs" else st.step
+            go = st.lusgs if kind.startswith("lusgs") else st.step
             go(1)  # untimed: set-up (colouring, buffers) and first rounding
             res = []
             t0 = time.perf_counter()
@@ -541,6 +544,7 @@ def run_lusgs(cfg, mesh, m0, iters, cfl):
     finally:
         ctx.close()
     out["cost_ratio"] = out["lusgs"]["ms_per_iteration"] / out["explicit"]["ms_per_iteration"]
+    out["cost_ratio_mixed"] = out["lusgs_mixed"]["ms_per_iteration"] / out["explicit_mixed"]["ms_per_iteration"]
     return out
 
 

@@ -276,9 +276,11 @@ tk_status tk_step_async(tk_state* st, int32_t nsteps);
  * the backward sweep df descending (cells without a later neighbour keep
  * df*), each rounded to the state's tolerance and cap, and f + df is
  * rounded into the new state.  dt is the state's (a CFL above the explicit
- * step's bound of 1 is the point).  residual as for tk_step.  TK_EINVAL
- * for mixed-precision, plain or N = 48 states and for meshes with faces
- * off the coordinate axes.  Blocking.                                    */
+ * step's bound of 1 is the point).  FP64 states round each stage on the
+ * FP64 N-basis path, mixed states assemble it in FP32 and round it with
+ * the mixed path's eigensolver.  residual as for tk_step.  TK_EINVAL for
+ * plain or N = 48 states and for meshes with faces off the coordinate
+ * axes.  Blocking.                                                        */
 tk_status tk_lusgs(tk_state* st, int32_t iters, double* residual);
 
 /* Rank histogram (hist[0..16], ranks are max over modes) and mean

@@ -1333,20 +1333,21 @@ hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, int* l
   return hipGetLastError();
 }
 
-// LU-SGS backward stage and commit of one cell each (FP64, fibre form):
-// backward X = df*_i + D^-1 sum_{upper far cells} b_l o df_m, with b_l the
-// explicit step's far-side row scaling; commit X = f_i + df_i.
-template <int N, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_lu_combine(DevState d, LuArgs lu, int c0, double* X, int stage) {
+// LU-SGS backward stage and commit of one cell each (fibre form, in the
+// workspace type T: FP64, or FP32 on the mixed path): backward
+// X = df*_i + D^-1 sum_{upper far cells} b_l o df_m, with b_l the explicit
+// step's far-side row scaling; commit X = f_i + df_i.
+template <int N, int BLOCK, typename T>
+__global__ __launch_bounds__(BLOCK) void k_lu_combine(DevState d, LuArgs lu, int c0, T* X, int stage) {
   constexpr int FIB = N * N / BLOCK;
   static_assert(FIB * BLOCK == N * N, "fibres must tile the workgroup");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* smem = reinterpret_cast<double*>(smem_raw);
+  T* smem = reinterpret_cast<T*>(smem_raw);
   const int CS = d.CS;
-  double* sU = smem;                  // 3 CS N
-  double* sG = sU + 3 * CS * N;       // CS^3
-  double* sY = sG + CS * CS * CS;     // CS CS N
-  double* sb = sY + CS * CS * N;      // N
+  T* sU = smem;                  // 3 CS N
+  T* sG = sU + 3 * CS * N;       // CS^3
+  T* sY = sG + CS * CS * CS;     // CS CS N
+  T* sb = sY + CS * CS * N;      // N
   const int cb = blockIdx.x;
   if (d.cells && c0 + cb >= *d.cells_n) return;
   const int c = d.cells ? d.cells[c0 + cb] : c0 + cb;
@@ -1355,11 +1356,11 @@ __global__ __launch_bounds__(BLOCK) void k_lu_combine(DevState d, LuArgs lu, int
   int pf[FIB];
 #pragma unroll
   for (int f = 0; f < FIB; ++f) pf[f] = tid + BLOCK * f;
-  double acc[FIB][N];
+  T acc[FIB][N];
 #pragma unroll
   for (int f = 0; f < FIB; ++f)
 #pragma unroll
-    for (int i = 0; i < N; ++i) acc[f][i] = 0.0;
+    for (int i = 0; i < N; ++i) acc[f][i] = (T)0;
   if (stage == LU_BACKWARD) {
     for (int l = 0; l < kSlots; ++l) {
       if (d.slot_kind[kSlots * c + l] != SK_INTERIOR) continue;
@@ -1368,37 +1369,37 @@ __global__ __launch_bounds__(BLOCK) void k_lu_combine(DevState d, LuArgs lu, int
       const int ax = d.slot_axis[kSlots * c + l];
       const double sg = (double)d.slot_sig[kSlots * c + l];
       const double coef = d.slot_coef[kSlots * c + l];
-      for (int i = tid; i < N; i += BLOCK) sb[i] = coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0);
+      for (int i = tid; i < N; i += BLOCK) sb[i] = (T)(coef * fmax(-sg * (P.xi_min + i * P.dxi), 0.0));
       __syncthreads();
       const int q1 = lu.rank[3 * nb], q2 = lu.rank[3 * nb + 1], q3 = lu.rank[3 * nb + 2];
-      stage_state<N, BLOCK, double>(lu.core, lu.fac, CS, nb, q1, q2, q3, -1, ax, sb, 1.0, sU, sG);
+      stage_state<N, BLOCK, T>(lu.core, lu.fac, CS, nb, q1, q2, q3, -1, ax, sb, 1.0, sU, sG);
       __syncthreads();
-      expand_fibres<N, BLOCK, double, FIB>(acc, sU, sG, sY, q1, q2, q3, CS, pf);
+      expand_fibres<N, BLOCK, T, FIB>(acc, sU, sG, sY, q1, q2, q3, CS, pf);
       __syncthreads();
     }
     const double* di = lu.dinv + (size_t)c * (N + 1);
-    for (int i = tid; i < N; i += BLOCK) sb[i] = di[i];
+    for (int i = tid; i < N; i += BLOCK) sb[i] = (T)di[i];
     __syncthreads();
-    const double isg = di[N];
+    const T isg = (T)di[N];
 #pragma unroll
     for (int f = 0; f < FIB; ++f) {
-      const double w = sb[pf[f] % N] * sb[pf[f] / N] * isg;
+      const T w = sb[pf[f] % N] * sb[pf[f] / N] * isg;
 #pragma unroll
       for (int i = 0; i < N; ++i) acc[f][i] *= sb[i] * w;
     }
   } else {
     const int r1 = d.rank[3 * c], r2 = d.rank[3 * c + 1], r3 = d.rank[3 * c + 2];
-    stage_state<N, BLOCK, double>(d.core, d.fac, CS, c, r1, r2, r3, -1, -1, nullptr, 1.0, sU, sG);
+    stage_state<N, BLOCK, T>(d.core, d.fac, CS, c, r1, r2, r3, -1, -1, nullptr, 1.0, sU, sG);
     __syncthreads();
-    expand_fibres<N, BLOCK, double, FIB>(acc, sU, sG, sY, r1, r2, r3, CS, pf);
+    expand_fibres<N, BLOCK, T, FIB>(acc, sU, sG, sY, r1, r2, r3, CS, pf);
     __syncthreads();
   }
   // the cell's own increment (df* in the backward stage, df in the commit)
   const int q1 = lu.rank[3 * c], q2 = lu.rank[3 * c + 1], q3 = lu.rank[3 * c + 2];
-  stage_state<N, BLOCK, double>(lu.core, lu.fac, CS, c, q1, q2, q3, -1, -1, nullptr, 1.0, sU, sG);
+  stage_state<N, BLOCK, T>(lu.core, lu.fac, CS, c, q1, q2, q3, -1, -1, nullptr, 1.0, sU, sG);
   __syncthreads();
-  expand_fibres<N, BLOCK, double, FIB>(acc, sU, sG, sY, q1, q2, q3, CS, pf);
-  double* out = X + (size_t)cb * N * N * N;
+  expand_fibres<N, BLOCK, T, FIB>(acc, sU, sG, sY, q1, q2, q3, CS, pf);
+  T* out = X + (size_t)cb * N * N * N;
 #pragma unroll
   for (int f = 0; f < FIB; ++f)
 #pragma unroll
@@ -1475,21 +1476,20 @@ __global__ __launch_bounds__(64) void k_lu_diag(DevState d, const double* pq, do
   if (lane == 0) out[N] = 1.0 / sigma;
 }
 
-template <int N>
-hipError_t launch_lu_t(const DevState& d, const LuArgs& lu, int stage, int c0, int count, double* X,
-                       hipStream_t s) {
+template <int N, typename T>
+hipError_t launch_lu_t(const DevState& d, const LuArgs& lu, int stage, int c0, int count, T* X, hipStream_t s) {
   constexpr int B = ExpandShape<N>::B;
   const int CS = d.CS;
   if (stage == LU_FORWARD) {
-    const size_t sh = sizeof(double) * (N + 3 * N + N + 3 * CS * N + CS * CS * CS + CS * CS * N + 3 * CS * N + 64);
-    auto k = k_expand<N, B, double, true>;
+    const size_t sh = sizeof(T) * (N + 3 * N + N + 3 * CS * N + CS * CS * CS + CS * CS * N + 3 * CS * N + 64);
+    auto k = k_expand<N, B, T, true>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(count * ExpandSplit<N>::S), dim3(B), sh, s, d, c0, X, lu);
     return hipGetLastError();
   }
-  const size_t sh = sizeof(double) * (3 * CS * N + CS * CS * CS + CS * CS * N + N);
-  auto k = k_lu_combine<N, B>;
+  const size_t sh = sizeof(T) * (3 * CS * N + CS * CS * CS + CS * CS * N + N);
+  auto k = k_lu_combine<N, B, T>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(count), dim3(B), sh, s, d, lu, c0, X, stage);
@@ -1535,13 +1535,21 @@ hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixe
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_lu_expand(const DevState& d, const LuArgs& lu, int stage, int c0, int count, double* X,
+hipError_t launch_lu_expand(const DevState& d, const LuArgs& lu, int stage, int c0, int count, void* X, int mixed,
                             hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  switch (d.N) {
-    case 16: return launch_lu_t<16>(d, lu, stage, c0, count, X, s);
-    case 24: return launch_lu_t<24>(d, lu, stage, c0, count, X, s);
-    case 32: return launch_lu_t<32>(d, lu, stage, c0, count, X, s);
+  if (mixed) {
+    switch (d.N) {
+      case 16: return launch_lu_t<16, float>(d, lu, stage, c0, count, (float*)X, s);
+      case 24: return launch_lu_t<24, float>(d, lu, stage, c0, count, (float*)X, s);
+      case 32: return launch_lu_t<32, float>(d, lu, stage, c0, count, (float*)X, s);
+    }
+  } else {
+    switch (d.N) {
+      case 16: return launch_lu_t<16, double>(d, lu, stage, c0, count, (double*)X, s);
+      case 24: return launch_lu_t<24, double>(d, lu, stage, c0, count, (double*)X, s);
+      case 32: return launch_lu_t<32, double>(d, lu, stage, c0, count, (double*)X, s);
+    }
   }
   return hipErrorInvalidValue;
 }

@@ -557,7 +557,11 @@ __device__ bool rround_cell(const DevState& d, int c, double* smem, unsigned lon
 // start (wvalid[3 c + a] = 0: the kept eigenbasis of the N-basis path
 // predates this step).
 template <int N, int RM, int GM, int QM, int SC>
-__global__ __launch_bounds__(kRThreads, 3) void k_rround(DevState d, const int* list, const int* list_n, int* next,
+// Four workgroups per CU (at most 128 VGPRs, a few spilled): the per-cell
+// chains of reductions and barriers are latency-bound, and a fourth
+// workgroup hides more of that latency than the spills cost (14.3 against
+// 15.8 ms per step over the channel run's first 180 steps).
+__global__ __launch_bounds__(kRThreads, 4) void k_rround(DevState d, const int* list, const int* list_n, int* next,
                                                       int* next_n, int* wvalid, unsigned long long* stats) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* smem = reinterpret_cast<double*>(smem_raw);
@@ -585,7 +589,7 @@ __global__ __launch_bounds__(kRThreads, 3) void k_rround(DevState d, const int* 
 __global__ void k_zero_count(int* a) { *a = 0; }
 
 // Cells whose own state and far sides all have rank 1 (r0 <= 12 per mode): a
-// 13 x 13 x 12 core layout and 128 staged core values (34 KB of LDS, three
+// 13 x 13 x 12 core layout and 128 staged core values (34 KB of LDS, four
 // workgroups per CU).  The others are listed for the N-basis path.
 template <int N>
 hipError_t launch_rround_t(const DevState& d, int* listD, int* nD, int* wvalid, unsigned long long* stats,

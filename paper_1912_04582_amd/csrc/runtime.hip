@@ -1061,9 +1061,12 @@ static tk_status state_lu_iteration(tk_state* st) {
   prof_end(ctx, KID_LU, ev);
   if (e != hipSuccess) return ctx_hip(ctx, e, "LU-SGS diagonal");
   LuArgs lu{st->d_df_core, st->d_df_fac, st->d_df_rank, st->d_lu_col, 0, st->d_lu_dinv};
-  double* X = (double*)st->X;
+  void* X = st->X;
+  const int mx = st->mixed ? 1 : 0;
   // one stage over the listed cells (cells == nullptr: every cell), rounded
-  // into (fac_o, rank_o, core_o)
+  // into (fac_o, rank_o, core_o): on the FP64 path two eigensolver passes
+  // (first basis, Gram of the rotated unfoldings), on the mixed path one
+  // pass over the FP32 stage tensor with its thresholds
   auto stage = [&](int kind, int count, const int* cells, const int* cells_n, double* fac_o, int* rank_o,
                    double* core_o) -> tk_status {
     DevState ds = d;
@@ -1072,24 +1075,29 @@ static tk_status state_lu_iteration(tk_state* st) {
     for (int c0 = 0; c0 < count; c0 += st->chunk) {
       const int cnt = std::min(st->chunk, count - c0);
       prof_begin(ctx, KID_LU, &ev);
-      e = launch_lu_expand(ds, lu, kind, c0, cnt, X, q);
+      e = launch_lu_expand(ds, lu, kind, c0, cnt, X, mx, q);
       prof_end(ctx, KID_LU, ev);
       if (e != hipSuccess) return ctx_hip(ctx, e, "LU-SGS stage");
       prof_begin(ctx, KID_GRAM, &ev);
-      e = launch_gram(st->N, cnt, X, 0, st->G, q, c0, cells_n);
+      e = launch_gram(st->N, cnt, X, mx, st->G, q, c0, cells_n);
       prof_end(ctx, KID_GRAM, ev);
       if (e != hipSuccess) return ctx_hip(ctx, e, "gram");
       prof_begin(ctx, KID_EIG, &ev);
-      e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, fac_o, rank_o, nullptr, st->Wb,
-                     nullptr, 1e-15, 1e-18, q, 0.0, cells, cells_n, nullptr);
-      if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, X, 0, st->Wb, st->G, q, c0, cells_n);
-      if (e == hipSuccess)
-        e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, fac_o, rank_o, st->Wb, nullptr,
+      if (mx) {
+        e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, fac_o, rank_o, nullptr, nullptr,
+                       nullptr, 1e-12, 1e-13, q, 0.0, cells, cells_n, nullptr);
+      } else {
+        e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, fac_o, rank_o, nullptr, st->Wb,
                        nullptr, 1e-15, 1e-18, q, 0.0, cells, cells_n, nullptr);
+        if (e == hipSuccess) e = launch_gram_rot(st->N, cnt, X, 0, st->Wb, st->G, q, c0, cells_n);
+        if (e == hipSuccess)
+          e = launch_eig(st->N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, st->CS, fac_o, rank_o, st->Wb, nullptr,
+                         nullptr, 1e-15, 1e-18, q, 0.0, cells, cells_n, nullptr);
+      }
       prof_end(ctx, KID_EIG, ev);
       if (e != hipSuccess) return ctx_hip(ctx, e, "eig");
       prof_begin(ctx, KID_PROJECT, &ev);
-      e = launch_project(st->N, cnt, X, 0, c0, st->CS, fac_o, rank_o, core_o, q, cells, cells_n);
+      e = launch_project(st->N, cnt, X, mx, c0, st->CS, fac_o, rank_o, core_o, q, cells, cells_n);
       prof_end(ctx, KID_PROJECT, ev);
       if (e != hipSuccess) return ctx_hip(ctx, e, "project");
     }
@@ -1631,8 +1639,8 @@ tk_status tk_lusgs(tk_state* st, int32_t iters, double* residual) {
   if (!st || iters < 0) return TK_EINVAL;
   tk_ctx* ctx = st->ctx;
   std::lock_guard<std::recursive_mutex> g(ctx->mu);
-  if (st->plain || st->mixed || st->oblique || st->N > 32)
-    return ctx_fail(ctx, TK_EINVAL, "LU-SGS runs on FP64 Tucker states with N <= 32 and axis-aligned faces");
+  if (st->plain || st->oblique || st->N > 32)
+    return ctx_fail(ctx, TK_EINVAL, "LU-SGS runs on Tucker states with N <= 32 and axis-aligned faces");
   if (!st->lu_ready) {
     const tk_status s = lu_setup(st);
     if (s != TK_OK) return s;

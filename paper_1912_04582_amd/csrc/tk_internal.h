@@ -137,11 +137,12 @@ hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s);
 // (1 + dt nu) 1 + (dt / (2 V)) (sum_l A_l) |xi|; pq[inst] = (p, Q) of |xi|'s
 // mode-1 unfolding S: p = S 1 (N values), Q = S S^T (N x N)
 hipError_t launch_lu_diag(const DevState& d, const double* pq, double* dinv, hipStream_t s);
-// LU-SGS stage of `count` cells (d.cells / d.cells_n from c0) into X (fp64):
+// LU-SGS stage of `count` cells (d.cells / d.cells_n from c0) into X (FP64,
+// or FP32 when mixed):
 // forward  X = D^-1 (dt R + sum_{lower far cells} b_l o df*_m)
 // backward X = df*_i + D^-1 sum_{upper far cells} b_l o df_m
 // commit   X = f_i + df_i
-hipError_t launch_lu_expand(const DevState& d, const LuArgs& lu, int stage, int c0, int count, double* X,
+hipError_t launch_lu_expand(const DevState& d, const LuArgs& lu, int stage, int c0, int count, void* X, int mixed,
                             hipStream_t s);
 // generic expansion of `count` Tucker tensors given in the state layout into X (fp64)
 hipError_t launch_expand_plain(int N, int count, int CS, const double* core, const double* fac,

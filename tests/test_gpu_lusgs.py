@@ -19,11 +19,11 @@ def ctx():
     c.close()
 
 
-def channel_case(N, cap, tol, init, cfl, seed=21, Kn=0.1):
+def channel_case(N, cap, tol, init, cfl, seed=21, Kn=0.1, precision="fp64"):
     m = synth.channel_with_obstacle(nx=8, ny=4, nz=4, h=0.25, obstacle=((3, 5), (1, 3), (1, 3)),
                                     inflow=(1.0, (0.9, 0.0, 0.0), 1.0), Tw=1.4)
     cfg = dict(N=N, xi_max=4.5, cap=cap, tol=tol, cfl=cfl, Pr=2 / 3, omega=0.5, Kn=Kn, Rg=0.5, m=1.0,
-               seed=seed, init=init, precision="fp64")
+               seed=seed, init=init, precision=precision)
     return m, cfg, synth.initial_macros(cfg, m)
 
 
@@ -36,16 +36,18 @@ def oracle_run(m, cfg, m0, iters):
 
 
 CASES = [
-    # N, cap, tol, init, CFL, iterations
-    (16, 6, 1e-6, "random", 4.0, 3),
-    (24, 8, 1e-6, "freestream", 8.0, 3),
-    (32, 12, 1e-5, "random", 4.0, 2),
+    # N, cap, tol, init, CFL, iterations, precision, bar
+    (16, 6, 1e-6, "random", 4.0, 3, "fp64", 1e-10),
+    (24, 8, 1e-6, "freestream", 8.0, 3, "fp64", 1e-10),
+    (32, 12, 1e-5, "random", 4.0, 2, "fp64", 1e-10),
+    (32, 12, 1e-5, "random", 4.0, 2, "mixed", 1e-5),
+    (24, 8, 1e-6, "freestream", 8.0, 3, "mixed", 1e-5),
 ]
 
 
-@pytest.mark.parametrize("N,cap,tol,init,cfl,iters", CASES)
-def test_lusgs_matches_oracle(ctx, N, cap, tol, init, cfl, iters):
-    m, cfg, m0 = channel_case(N, cap, tol, init, cfl)
+@pytest.mark.parametrize("N,cap,tol,init,cfl,iters,precision,bar", CASES)
+def test_lusgs_matches_oracle(ctx, N, cap, tol, init, cfl, iters, precision, bar):
+    m, cfg, m0 = channel_case(N, cap, tol, init, cfl, precision=precision)
     mesh = tk.Mesh(ctx, m)
     st = tk.State(ctx, mesh, cfg, m0)
     res = st.lusgs(iters, residual=True)
@@ -55,11 +57,12 @@ def test_lusgs_matches_oracle(ctx, N, cap, tol, init, cfl, iters):
     mesh.close()
     ref, oranks = oracle_run(m, cfg, m0, iters)
     err, _ = macro_rel_err(got, ref)
-    print(f"LU-SGS N={N} CFL {cfl} {iters} iterations: max rel macro err {err:.3e}, "
+    print(f"LU-SGS N={N} {precision} CFL {cfl} {iters} iterations: max rel macro err {err:.3e}, "
           f"residual {res[0]:.3e}, rank mismatches {(ranks != oranks).any(1).sum()}")
     assert np.isfinite(res).all() and res[0] > 0
-    assert err < 1e-10, err
-    assert (ranks == oranks).all()
+    assert err < bar, err
+    if precision == "fp64":
+        assert (ranks == oranks).all()
 
 
 def test_lusgs_batch_matches_oracle(ctx):
@@ -103,7 +106,7 @@ def test_lusgs_keeps_an_equilibrium(ctx):
 def test_lusgs_refuses_unsupported_states(ctx):
     m, cfg, m0 = channel_case(16, 6, 1e-6, "random", 4.0)
     mesh = tk.Mesh(ctx, m)
-    st = tk.State(ctx, mesh, dict(cfg, precision="mixed"), m0)
+    st = tk.State(ctx, mesh, cfg, m0, plain=True)
     with pytest.raises(tk.TkError) as e:
         st.lusgs(1)
     assert e.value.status == tk.TK_EINVAL
