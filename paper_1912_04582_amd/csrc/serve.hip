@@ -446,7 +446,10 @@ tk_status tk_serve_submit(tk_server* srv, const tk_request* req, uint64_t* ticke
   r->params = req->params;
   r->max_steps = req->max_steps;
   r->res_tol = req->residual_tol;
-  r->bytes = state_bytes_estimate(nc, req->params, false, nc);
+  // served states lay every cell out for the largest rank cap
+  tk_params pm = req->params;
+  pm.rank_cap = tk::kMaxCap;
+  r->bytes = state_bytes_estimate(nc, pm, false, nc);
   for (int f = 0; f < nf && !r->oblique; ++f) r->oblique = face_axis(&r->fn[3 * (size_t)f]) < 0;
   std::lock_guard<std::mutex> g(srv->mu);
   if (srv->stop) return TK_EBUSY;
