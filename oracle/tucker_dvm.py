@@ -11,7 +11,9 @@ velocity method"):
   4. the update f + dt R as a sum of terms: (1 - dt nu) f, dt nu f_S and,
      per face, -(dt A/V) P_out o f and -(dt A/V) P_in o g (Op3 products);
   5. one Op4 rounding of the Op2 sum of those terms.
-In exact arithmetic this equals O1 (the same tensor is rounded).
+In exact arithmetic this equals O1 (the same tensor is rounded).  step_faces
+is the variant with the paper's intermediate roundings: each face's pair of
+terms rounded on its own before the final sum.
 """
 
 import numpy as np
@@ -45,24 +47,32 @@ def ghost_tucker(S, j, f):
     raise ValueError(f"unknown boundary kind {kind}")
 
 
-def update_terms(S, i, get):
-    """The Tucker terms whose sum is f* for cell i, and the macros of f_i."""
+def grouped_terms(S, i, get):
+    """The terms of f* for cell i grouped by origin: the cell's own terms
+    [(1 - dt nu) f, dt nu f_S], then per face the pair
+    [-(dt A/V) P_out o f, -(dt A/V) P_in o g]; and the macros of f_i."""
     mesh = S.mesh
     f = get(i)
     n, u, T, q = kin.macros_tucker(f, S.xi, S.dxi, S.Rg, S.m)
     nu = kin.collision_freq(n, T, S.Kn, S.omega, S.Rg, S.m)
     fs = kin.fs_tucker(n, u, T, q, S.xi, S.Pr, S.Rg, S.m)
     dt = S.dt
-    terms = [f.scaled(1.0 - dt * nu), fs.scaled(dt * nu)]
+    own = [f.scaled(1.0 - dt * nu), fs.scaled(dt * nu)]
+    faces = []
     V = mesh["cell_volume"][i]
     for j, s in S.cell_faces[i]:
         c = -dt * mesh["face_area"][j] / V
         pout, pin = S.p_terms(j, s)
         nb = mesh["face_right"][j] if s > 0 else mesh["face_left"][j]
         g = get(nb) if nb >= 0 else ghost_tucker(S, j, f)
-        terms.append(tk.hadamard(pout, f).scaled(c))
-        terms.append(tk.hadamard(pin, g).scaled(c))
-    return terms, (n, u, T, q)
+        faces.append([tk.hadamard(pout, f).scaled(c), tk.hadamard(pin, g).scaled(c)])
+    return own, faces, (n, u, T, q)
+
+
+def update_terms(S, i, get):
+    """The Tucker terms whose sum is f* for cell i, and the macros of f_i."""
+    own, faces, mac = grouped_terms(S, i, get)
+    return own + [t for pair in faces for t in pair], mac
 
 
 def step(S, states, cells=None):
@@ -74,6 +84,25 @@ def step(S, states, cells=None):
     for i in cells:
         terms, _ = update_terms(S, i, get)
         out[i] = tk.round_sum(terms, S.tol, S.cap)
+    return out
+
+
+def step_faces(S, states, cells=None):
+    """The step with the paper's intermediate rounding placement (Section
+    "Tensorized discrete velocity method": a rounding after each operation
+    that can raise the ranks a lot): each face's flux term, the Op2 sum of
+    its two Op3 products (ranks of P_out, P_in times those of f, g), is
+    rounded to the relative accuracy eps and the cap on its own; the
+    rounded face terms are then summed with the cell's own terms and the sum
+    rounded once more.  With eps -> 0 it is the step above."""
+    get = (lambda c: states[c])
+    if cells is None:
+        cells = range(S.mesh["n_cells"])
+    out = {}
+    for i in cells:
+        own, faces, _ = grouped_terms(S, i, get)
+        rounded = [tk.round_sum(pair, S.tol, S.cap) for pair in faces]
+        out[i] = tk.round_sum(own + rounded, S.tol, S.cap)
     return out
 
 
@@ -106,8 +135,9 @@ def cone(S, targets, steps):
     return [sorted(l) for l in levels]
 
 
-def run_cone(S, macros0, targets, steps, full_path=False):
-    """Advance only the dependency cone of `targets`; O2 (or O1) states."""
+def run_cone(S, macros0, targets, steps, full_path=False, faces=False):
+    """Advance only the dependency cone of `targets`; O2 (or O1) states
+    (faces: the intermediate-rounding step, step_faces)."""
     from . import dvm
     levels = cone(S, targets, steps)
     if full_path:
@@ -118,8 +148,9 @@ def run_cone(S, macros0, targets, steps, full_path=False):
             last = st
         return last if steps else {i: tk.hosvd(F[i], 0.0, S.N) for i in levels[0]}
     st = initial_states(S, macros0, levels[0])
+    adv = step_faces if faces else step
     for s in range(1, steps + 1):
-        st = step(S, st, levels[s])
+        st = adv(S, st, levels[s])
     return st
 
 
