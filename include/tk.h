@@ -283,6 +283,23 @@ tk_status tk_step_async(tk_state* st, int32_t nsteps);
  * axes.  Blocking.                                                        */
 tk_status tk_lusgs(tk_state* st, int32_t iters, double* residual);
 
+/* Intermediate rounding (Section "Tensorized discrete velocity method": a
+ * rounding after each operation that can raise the Tucker ranks a lot).
+ * With on = 1 every later step of st rounds each face's flux term,
+ *   E_l = -(dt A_l / V) (P_out o f + P_in o g_l)
+ * (P_out/in = max/min(s xi_a, 0) on an axis-aligned face, (xi_n +- est_l)/2
+ * with the |xi.e| estimate on an oblique one; g_l the far side or ghost),
+ * to the instance's relative accuracy and rank cap on its own, then rounds
+ * the sum (1 - dt nu) f + dt nu f_S + sum_l E~_l once more.  With eps -> 0
+ * this is the exact update that on = 0 (the default) rounds once; otherwise
+ * the two differ by at most eps (sum_l |E_l| + |f*|) per cell.  Every cell
+ * takes the N-basis path, eagerly on the context stream (no graph replay,
+ * no pass-size trials), with the precision's eigensolver (FP64: two passes).
+ * The first enable allocates six state-sized buffers (TK_ENOMEM beyond the
+ * budget); they live as long as the state.  TK_EINVAL for plain states and
+ * a server's states.                                                      */
+tk_status tk_state_face_rounding(tk_state* st, int32_t on);
+
 /* Rank histogram (hist[0..16], ranks are max over modes) and mean
  * compression ratio C = (r1 r2 r3 + N (r1 + r2 + r3)) / N^3 (Section "Test
  * problem").                                                              */

@@ -1016,6 +1016,46 @@ __device__ inline void ob_tables(const DevState& d, int c, T* sxi, T* sd, double
   }
 }
 
+// f_S of the macroparameters M (Tucker form, ranks 4: factors base v^k,
+// k = 0..3, the 13 non-zero core entries of the Shakhov correction), core
+// scaled by `scale`, staged into the LDS layout with factor stride CSL.
+template <int N, int BLOCK, typename T>
+__device__ inline void stage_fs_any(const double* M, const InstParams& P, double scale, int CSL, T* sU, T* sG) {
+  const int tid = threadIdx.x;
+  const double n = M[0], T0 = M[4];
+  const double RT = P.Rg * T0;
+  const double amp = cbrt(n) / sqrt(2.0 * M_PI * RT);
+  const double beta = 1.0 / (2.0 * RT);
+  const double As = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * n * RT * RT);
+  for (int o = tid; o < 3 * N; o += BLOCK) {
+    const int a = o / N, i = o % N;
+    const double v = P.xi_min + i * P.dxi - M[1 + a];
+    const double bse = amp * exp(-v * v * beta);
+    sU[a * CSL * N + 0 * N + i] = (T)bse;
+    sU[a * CSL * N + 1 * N + i] = (T)(bse * v);
+    sU[a * CSL * N + 2 * N + i] = (T)(bse * v * v);
+    sU[a * CSL * N + 3 * N + i] = (T)(bse * v * v * v);
+  }
+  for (int o = tid; o < 64; o += BLOCK) {
+    const int k[3] = {o & 3, (o >> 2) & 3, o >> 4};
+    double g = 0.0;
+    int nz = 0, which = -1;
+    for (int a = 0; a < 3; ++a)
+      if (k[a]) { ++nz; which = a; }
+    if (nz == 0) {
+      g = 1.0;
+    } else if (nz == 1) {
+      if (k[which] == 1) g = -2.5 * As * M[5 + which];
+      else if (k[which] == 3) g = As * beta * M[5 + which];
+    } else if (nz == 2) {
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          if (a != b && k[a] == 1 && k[b] == 2 && k[3 - a - b] == 0) g = As * beta * M[5 + a];
+    }
+    sG[o] = (T)(scale * g);
+  }
+}
+
 // General path (any ranks): sources restaged for every pass of fibres.
 template <int N, int BLOCK, typename T>
 __device__ void ob_slow(const DevState& d, const int c, T* Xc, T* smem) {
@@ -1081,42 +1121,9 @@ __device__ void ob_slow(const DevState& d, const int c, T* Xc, T* smem) {
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[i] *= w[i];
     // ---- f_S, scaled by dt nu
-    {
-      const double n = M[0], T0 = M[4];
-      const double RT = P.Rg * T0;
-      const double amp = cbrt(n) / sqrt(2.0 * M_PI * RT);
-      const double beta = 1.0 / (2.0 * RT);
-      const double As = 2.0 * (1.0 - P.Pr) / (5.0 * P.m * n * RT * RT);
-      for (int o = tid; o < 3 * N; o += BLOCK) {
-        const int a = o / N, i = o % N;
-        const double v = P.xi_min + i * P.dxi - M[1 + a];
-        const double bse = amp * exp(-v * v * beta);
-        sU[a * CSL * N + 0 * N + i] = (T)bse;
-        sU[a * CSL * N + 1 * N + i] = (T)(bse * v);
-        sU[a * CSL * N + 2 * N + i] = (T)(bse * v * v);
-        sU[a * CSL * N + 3 * N + i] = (T)(bse * v * v * v);
-      }
-      for (int o = tid; o < 64; o += BLOCK) {
-        const int k[3] = {o & 3, (o >> 2) & 3, o >> 4};
-        double g = 0.0;
-        int nz = 0, which = -1;
-        for (int a = 0; a < 3; ++a)
-          if (k[a]) { ++nz; which = a; }
-        if (nz == 0) {
-          g = 1.0;
-        } else if (nz == 1) {
-          if (k[which] == 1) g = -2.5 * As * M[5 + which];
-          else if (k[which] == 3) g = As * beta * M[5 + which];
-        } else if (nz == 2) {
-          for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b)
-              if (a != b && k[a] == 1 && k[b] == 2 && k[3 - a - b] == 0) g = As * beta * M[5 + a];
-        }
-        sG[o] = (T)(P.dt * nu * g);
-      }
-      __syncthreads();
-      expand_pass<N, BLOCK, T>(acc, sU, sG, sY, sZ, 4, 4, 4, CSL, pbase);
-    }
+    stage_fs_any<N, BLOCK, T>(M, P, P.dt * nu, CSL, sU, sG);
+    __syncthreads();
+    expand_pass<N, BLOCK, T>(acc, sU, sG, sY, sZ, 4, 4, 4, CSL, pbase);
     // ---- far sides
     for (int l = 0; l < kSlots; ++l) {
       const int8_t kind = d.slot_kind[kSlots * c + l];
@@ -1223,6 +1230,190 @@ template <> struct OblShape<16> { static constexpr int B = 256; };
 template <> struct OblShape<24> { static constexpr int B = 288; };
 template <> struct OblShape<32> { static constexpr int B = 512; };
 template <> struct OblShape<48> { static constexpr int B = 384; };
+
+// ---- intermediate rounding of the face terms ---------------------------------
+// The variant of the step that rounds each face's flux term on its own before
+// the sum (the paper's placement of roundings after the rank-raising
+// operations).  k_face_term expands the contribution of face slot l to the
+// update, E_l = -(dt A_l / V) (P_out o f + P_in o g): on an axis-aligned face
+// P_out = max(s xi_a, 0), P_in = min(s xi_a, 0); on an oblique one
+// P_out/in = (xi_n +- est_l) / 2 with the |xi.e| estimate.  k_face_sum expands
+// (1 - dt nu) f + dt nu f_S + sum_l E~_l from the rounded face terms.  Both use
+// the general (any rank) staging of the oblique path; a cell without slot l
+// gets E_l = 0.
+
+// far side g of face slot l staged (the neighbour, the cell itself, the cell
+// with the face axis reversed, or the rank-1 boundary Maxwellian)
+template <int N, int BLOCK, typename T>
+__device__ inline void stage_far(const DevState& d, int c, int l, const InstParams& P, int CSL, T* sU, T* sG,
+                                 int (&q)[3]) {
+  const int kind = d.slot_kind[kSlots * c + l];
+  const int ax = d.slot_axis[kSlots * c + l];
+  const int nb = d.slot_nb[kSlots * c + l];
+  if (kind == SK_INTERIOR || kind == SK_OUTFLOW || kind == SK_SYM) {
+    const int src = (kind == SK_INTERIOR) ? nb : c;
+    q[0] = d.rank[3 * src];
+    q[1] = d.rank[3 * src + 1];
+    q[2] = d.rank[3 * src + 2];
+    stage_any<N, BLOCK, T>(d.core, d.fac, d.CS, (size_t)src, q, kind == SK_SYM ? ax : -1, -1, 0.0, 0.0, P.xi_min,
+                           P.dxi, 1.0, CSL, sU, sG);
+  } else {
+    q[0] = q[1] = q[2] = 1;
+    const double gsc = (kind == SK_WALL) ? d.nw[kSlots * c + l] : 1.0;
+    const double* bf = d.bc_fac + (size_t)nb * 3 * N;
+    for (int o = threadIdx.x; o < 3 * N; o += BLOCK) sU[(o / N) * CSL * N + o % N] = (T)bf[o];
+    if (threadIdx.x == 0) sG[0] = (T)gsc;
+  }
+}
+
+template <int N, int BLOCK, typename T>
+__global__ __launch_bounds__(BLOCK) void k_face_term(DevState d, int c0, T* X, int l) {
+  constexpr int NPASS = N * N / BLOCK;
+  static_assert(NPASS * BLOCK == N * N, "passes must tile the fibres");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int CS = d.CS;
+  const int CSL = CS > kEstCap ? CS : kEstCap;
+  T* sU = smem;                   // 3 CSL N
+  T* sG = sU + 3 * CSL * N;       // CSL^3
+  T* sY = sG + CSL * CSL * CSL;   // KC CSL N
+  T* sZ = sY + KC * CSL * N;      // KC BLOCK
+  __shared__ double s_nrm[3];
+  const int cb = blockIdx.x;
+  if (d.cells && c0 + cb >= *d.cells_n) return;
+  const int c = d.cells ? d.cells[c0 + cb] : c0 + cb;
+  const int tid = threadIdx.x;
+  T* Xc = X + (size_t)cb * N * N * N;
+  const int kind = d.slot_kind[kSlots * c + l];
+  if (kind == SK_NONE) {
+    for (int o = tid; o < N * N * N; o += BLOCK) Xc[o] = 0;
+    return;
+  }
+  const InstParams P = d.ip[d.inst[c]];
+  const int ax = d.slot_axis[kSlots * c + l];
+  const double sg = (double)d.slot_sig[kSlots * c + l];
+  const double cf = -d.slot_coef[kSlots * c + l];
+  // outward normal of an oblique face (the table exists only on states with
+  // oblique faces)
+  if (ax < 0 && tid < 3) s_nrm[tid] = d.slot_nrm[((size_t)kSlots * c + l) * 3 + tid];
+  const int rc[3] = {d.rank[3 * c], d.rank[3 * c + 1], d.rank[3 * c + 2]};
+  for (int pass = 0; pass < NPASS; ++pass) {
+    const int pbase = pass * BLOCK;
+    const int p = pbase + tid;
+    const int i2 = p % N, i3 = p / N;
+    T f[N], g[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) f[i] = g[i] = 0;
+    stage_any<N, BLOCK, T>(d.core, d.fac, CS, (size_t)c, rc, -1, -1, 0.0, 0.0, P.xi_min, P.dxi, 1.0, CSL, sU, sG);
+    __syncthreads();
+    expand_pass<N, BLOCK, T>(f, sU, sG, sY, sZ, rc[0], rc[1], rc[2], CSL, pbase);
+    int q[3];
+    stage_far<N, BLOCK, T>(d, c, l, P, CSL, sU, sG, q);
+    __syncthreads();
+    expand_pass<N, BLOCK, T>(g, sU, sG, sY, sZ, q[0], q[1], q[2], CSL, pbase);
+    T* out = Xc + (size_t)p * N;
+    if (ax >= 0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int ia = ax == 0 ? i : (ax == 1 ? i2 : i3);
+        const double x = sg * (P.xi_min + ia * P.dxi);
+        out[i] = (T)cf * ((T)fmax(x, 0.0) * f[i] + (T)fmin(x, 0.0) * g[i]);
+      }
+    } else {
+      T e[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) e[i] = 0;
+      const int ei = d.slot_est[kSlots * c + l];
+      const int re[3] = {d.est_rank[3 * ei], d.est_rank[3 * ei + 1], d.est_rank[3 * ei + 2]};
+      stage_any<N, BLOCK, T>(d.est_core, d.est_fac, kEstCap, (size_t)ei, re, -1, -1, 0.0, 0.0, P.xi_min, P.dxi, 1.0,
+                             CSL, sU, sG);
+      __syncthreads();
+      expand_pass<N, BLOCK, T>(e, sU, sG, sY, sZ, re[0], re[1], re[2], CSL, pbase);
+      const double x2 = s_nrm[1] * (P.xi_min + i2 * P.dxi) + s_nrm[2] * (P.xi_min + i3 * P.dxi);
+      const T h = (T)(0.5 * cf);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const T xn = (T)(s_nrm[0] * (P.xi_min + i * P.dxi) + x2);
+        out[i] = h * ((xn + e[i]) * f[i] + (xn - e[i]) * g[i]);
+      }
+    }
+  }
+}
+
+template <int N, int BLOCK, typename T>
+__global__ __launch_bounds__(BLOCK) void k_face_sum(DevState d, FaceStates fs, int c0, T* X) {
+  constexpr int NPASS = N * N / BLOCK;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int CS = d.CS;
+  const int CSL = CS > kEstCap ? CS : kEstCap;
+  T* sU = smem;
+  T* sG = sU + 3 * CSL * N;
+  T* sY = sG + CSL * CSL * CSL;
+  T* sZ = sY + KC * CSL * N;
+  const int cb = blockIdx.x;
+  if (d.cells && c0 + cb >= *d.cells_n) return;
+  const int c = d.cells ? d.cells[c0 + cb] : c0 + cb;
+  const int tid = threadIdx.x;
+  const InstParams P = d.ip[d.inst[c]];
+  const double nu = d.nu[c];
+  const double* M = d.macro + 8 * (size_t)c;
+  const int rc[3] = {d.rank[3 * c], d.rank[3 * c + 1], d.rank[3 * c + 2]};
+  T* Xc = X + (size_t)cb * N * N * N;
+  for (int pass = 0; pass < NPASS; ++pass) {
+    const int pbase = pass * BLOCK;
+    T acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = 0;
+    stage_any<N, BLOCK, T>(d.core, d.fac, CS, (size_t)c, rc, -1, -1, 0.0, 0.0, P.xi_min, P.dxi, 1.0 - P.dt * nu,
+                           CSL, sU, sG);
+    __syncthreads();
+    expand_pass<N, BLOCK, T>(acc, sU, sG, sY, sZ, rc[0], rc[1], rc[2], CSL, pbase);
+    stage_fs_any<N, BLOCK, T>(M, P, P.dt * nu, CSL, sU, sG);
+    __syncthreads();
+    expand_pass<N, BLOCK, T>(acc, sU, sG, sY, sZ, 4, 4, 4, CSL, pbase);
+    for (int l = 0; l < kSlots; ++l) {
+      if (d.slot_kind[kSlots * c + l] == SK_NONE) continue;
+      const int q[3] = {fs.rank[l][3 * c], fs.rank[l][3 * c + 1], fs.rank[l][3 * c + 2]};
+      stage_any<N, BLOCK, T>(fs.core[l], fs.fac[l], CS, (size_t)c, q, -1, -1, 0.0, 0.0, P.xi_min, P.dxi, 1.0, CSL,
+                             sU, sG);
+      __syncthreads();
+      expand_pass<N, BLOCK, T>(acc, sU, sG, sY, sZ, q[0], q[1], q[2], CSL, pbase);
+    }
+    T* out = Xc + (size_t)(pbase + tid) * N;
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = acc[i];
+  }
+}
+
+template <int N, typename T>
+size_t face_lds(int CS) {
+  const int CSL = CS > kEstCap ? CS : kEstCap;
+  return sizeof(T) * (3 * (size_t)CSL * N + (size_t)CSL * CSL * CSL + (size_t)KC * CSL * N + (size_t)KC * OblShape<N>::B);
+}
+
+template <int N, typename T>
+hipError_t launch_face_term_t(const DevState& d, int c0, int count, void* X, int slot, hipStream_t s) {
+  constexpr int B = OblShape<N>::B;
+  const size_t sh = face_lds<N, T>(d.CS);
+  auto k = k_face_term<N, B, T>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(count), dim3(B), sh, s, d, c0, (T*)X, slot);
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t launch_face_sum_t(const DevState& d, const FaceStates& fs, int c0, int count, void* X, hipStream_t s) {
+  constexpr int B = OblShape<N>::B;
+  const size_t sh = face_lds<N, T>(d.CS);
+  auto k = k_face_sum<N, B, T>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(count), dim3(B), sh, s, d, fs, c0, (T*)X);
+  return hipGetLastError();
+}
+
 
 template <int N, typename T>
 hipError_t launch_expand_obl_t(const DevState& d, int c0, int count, void* X, int* list, int* list_n,
@@ -1530,6 +1721,46 @@ hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixe
       case 16: return launch_expand_t<16, double>(d, c0, count, X, list, list_n, s);
       case 24: return launch_expand_t<24, double>(d, c0, count, X, list, list_n, s);
       case 32: return launch_expand_t<32, double>(d, c0, count, X, list, list_n, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_face_term(const DevState& d, int c0, int count, void* X, int mixed, int slot, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (slot < 0 || slot >= kSlots) return hipErrorInvalidValue;
+  if (mixed) {
+    switch (d.N) {
+      case 16: return launch_face_term_t<16, float>(d, c0, count, X, slot, s);
+      case 24: return launch_face_term_t<24, float>(d, c0, count, X, slot, s);
+      case 32: return launch_face_term_t<32, float>(d, c0, count, X, slot, s);
+      case 48: return launch_face_term_t<48, float>(d, c0, count, X, slot, s);
+    }
+  } else {
+    switch (d.N) {
+      case 16: return launch_face_term_t<16, double>(d, c0, count, X, slot, s);
+      case 24: return launch_face_term_t<24, double>(d, c0, count, X, slot, s);
+      case 32: return launch_face_term_t<32, double>(d, c0, count, X, slot, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_face_sum(const DevState& d, const FaceStates& fs, int c0, int count, void* X, int mixed,
+                           hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (mixed) {
+    switch (d.N) {
+      case 16: return launch_face_sum_t<16, float>(d, fs, c0, count, X, s);
+      case 24: return launch_face_sum_t<24, float>(d, fs, c0, count, X, s);
+      case 32: return launch_face_sum_t<32, float>(d, fs, c0, count, X, s);
+      case 48: return launch_face_sum_t<48, float>(d, fs, c0, count, X, s);
+    }
+  } else {
+    switch (d.N) {
+      case 16: return launch_face_sum_t<16, double>(d, fs, c0, count, X, s);
+      case 24: return launch_face_sum_t<24, double>(d, fs, c0, count, X, s);
+      case 32: return launch_face_sum_t<32, double>(d, fs, c0, count, X, s);
     }
   }
   return hipErrorInvalidValue;

@@ -893,8 +893,80 @@ static tk_status state_step_graph(tk_state* st) {
 
 // One step: a timed trial while the pass size is being chosen, a graph
 // replay when enabled, else eager launches.
+// The step with intermediate roundings: per pass of cells, each face slot's
+// flux term expanded and rounded into its buffer (tolerance and cap of the
+// cell's instance), then the cell's own terms plus the rounded face terms
+// expanded and rounded into the next state.  Every cell on the N-basis path,
+// one stream; the FP64 path refines each basis with a second eigensolver pass.
+static tk_status state_step_faces(tk_state* st) {
+  tk_ctx* ctx = st->ctx;
+  hipStream_t q = ctx->stream;
+  hipEvent_t ev;
+  hipError_t e;
+  DevState d = state_dev(st);
+  prof_begin(ctx, KID_MOMENTS, &ev);
+  e = launch_moments(d, q);
+  prof_end(ctx, KID_MOMENTS, ev);
+  if (e != hipSuccess) return ctx_hip(ctx, e, "moments");
+  const int nc = st->nc, N = st->N, CS = st->CS;
+  const int mx = st->mixed ? 1 : 0;
+  FaceStates fs;
+  for (int l = 0; l < kSlots; ++l) {
+    fs.core[l] = st->d_face_core + (size_t)l * nc * CS * CS * CS;
+    fs.fac[l] = st->d_face_fac + (size_t)l * nc * 3 * CS * N;
+    fs.rank[l] = st->d_face_rank + (size_t)l * nc * 3;
+  }
+  auto round_into = [&](int c0, int cnt, double* fac_o, int* rank_o, double* core_o) -> tk_status {
+    prof_begin(ctx, KID_GRAM, &ev);
+    e = launch_gram(N, cnt, st->X, mx, st->G, q);
+    prof_end(ctx, KID_GRAM, ev);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "gram");
+    prof_begin(ctx, KID_EIG, &ev);
+    if (mx) {
+      e = launch_eig(N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, CS, fac_o, rank_o, nullptr, nullptr, nullptr,
+                     1e-12, 1e-13, q);
+    } else {
+      e = launch_eig(N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, CS, fac_o, rank_o, nullptr, st->Wb, nullptr,
+                     1e-15, 1e-18, q);
+      if (e == hipSuccess) e = launch_gram_rot(N, cnt, st->X, 0, st->Wb, st->G, q);
+      if (e == hipSuccess)
+        e = launch_eig(N, cnt, st->G, st->d_inst, st->d_ip, c0, 0.0, 0, CS, fac_o, rank_o, st->Wb, nullptr, nullptr,
+                       1e-15, 1e-18, q);
+    }
+    prof_end(ctx, KID_EIG, ev);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "eig");
+    prof_begin(ctx, KID_PROJECT, &ev);
+    e = launch_project(N, cnt, st->X, mx, c0, CS, fac_o, rank_o, core_o, q);
+    prof_end(ctx, KID_PROJECT, ev);
+    return e == hipSuccess ? TK_OK : ctx_hip(ctx, e, "project");
+  };
+  tk_status s = TK_OK;
+  for (int c0 = 0; c0 < nc && s == TK_OK; c0 += st->chunk) {
+    const int cnt = std::min(st->chunk, nc - c0);
+    for (int l = 0; l < kSlots && s == TK_OK; ++l) {
+      prof_begin(ctx, KID_EXPAND, &ev);
+      e = launch_face_term(d, c0, cnt, st->X, mx, l, q);
+      prof_end(ctx, KID_EXPAND, ev);
+      if (e != hipSuccess) return ctx_hip(ctx, e, "face term");
+      s = round_into(c0, cnt, const_cast<double*>(fs.fac[l]), const_cast<int*>(fs.rank[l]),
+                     const_cast<double*>(fs.core[l]));
+    }
+    if (s != TK_OK) break;
+    prof_begin(ctx, KID_EXPAND, &ev);
+    e = launch_face_sum(d, fs, c0, cnt, st->X, mx, q);
+    prof_end(ctx, KID_EXPAND, ev);
+    if (e != hipSuccess) return ctx_hip(ctx, e, "face sum");
+    s = round_into(c0, cnt, d.fac_n, d.rank_n, d.core_n);
+  }
+  if (s != TK_OK) return s;
+  if (!st->capturing) st->dense_total += nc;
+  st->cur ^= 1;
+  return TK_OK;
+}
+
 static tk_status state_step(tk_state* st) {
   tk_ctx* ctx = st->ctx;
+  if (st->face_round) return state_step_faces(st);
   if (st->tune == 1 && st->tune_skip > 0) {
     --st->tune_skip;
     return state_step_once(st);
@@ -1646,6 +1718,27 @@ tk_status tk_lusgs(tk_state* st, int32_t iters, double* residual) {
     if (s != TK_OK) return s;
   }
   return state_steps(st, iters, residual, true, true);
+}
+
+tk_status tk_state_face_rounding(tk_state* st, int32_t on) {
+  if (!st) return TK_EINVAL;
+  tk_ctx* ctx = st->ctx;
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  if (st->plain || st->served)
+    return ctx_fail(ctx, TK_EINVAL, "intermediate rounding runs on Tucker states outside a server");
+  if (on && !st->d_face_core) {
+    const size_t nc = st->nc, CS = st->CS, N = st->N;
+    tk_status s = TK_OK;
+    double* core = (double*)st_alloc(st, sizeof(double) * kSlots * nc * CS * CS * CS, &s);
+    double* fac = s == TK_OK ? (double*)st_alloc(st, sizeof(double) * kSlots * nc * 3 * CS * N, &s) : nullptr;
+    int* rank = s == TK_OK ? (int*)st_alloc(st, sizeof(int) * kSlots * nc * 3, &s) : nullptr;
+    if (s != TK_OK) return s;
+    st->d_face_core = core;
+    st->d_face_fac = fac;
+    st->d_face_rank = rank;
+  }
+  st->face_round = on != 0;
+  return TK_OK;
 }
 
 tk_status tk_step_async(tk_state* st, int32_t nsteps) {

@@ -76,6 +76,14 @@ struct DevState {
   const int* cells_n;
 };
 
+// Intermediate rounding: the rounded flux term of every face slot, each in the
+// state layout (core [nc][CS^3], factors [nc][3][CS][N], ranks [nc][3]).
+struct FaceStates {
+  const double* core[kSlots];
+  const double* fac[kSlots];
+  const int* rank[kSlots];
+};
+
 // LU-SGS sweeps: the increments (state layout) of the cells already swept,
 // the sweep colour of every cell and the rank-1 inverse diagonal.
 struct LuArgs {
@@ -123,6 +131,12 @@ hipError_t launch_gram_rot(int N, int count, const void* X, int mixed, const dou
 hipError_t launch_project(int N, int count, const void* X, int mixed, int c0, int CS, const double* fac_n,
                           const int* rank_n, double* core_n, hipStream_t s, const int* cells = nullptr,
                           const int* cells_n = nullptr);
+// Intermediate rounding of the face terms: X = the contribution of face slot
+// `slot` to the update (zero for cells without that slot), or the sum of the
+// cell's own terms and the rounded face terms fs
+hipError_t launch_face_term(const DevState& d, int c0, int count, void* X, int mixed, int slot, hipStream_t s);
+hipError_t launch_face_sum(const DevState& d, const FaceStates& fs, int c0, int count, void* X, int mixed,
+                           hipStream_t s);
 // Rounding in the space of the concatenated factors, fused with the term
 // assembly (axis-aligned faces, rank-1 neighbourhoods): every cell of d is
 // tried; the cells it leaves go to listD/nD for the N-basis path.

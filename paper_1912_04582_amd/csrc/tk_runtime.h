@@ -152,6 +152,12 @@ struct tk_state {
   int* d_df_rank = nullptr;
   double* d_lu_dinv = nullptr;
   double* d_lu_pq = nullptr;
+  // intermediate rounding of the face terms (set up on first use): the
+  // rounded flux term of every face slot, six state-layout buffers
+  bool face_round = false;
+  double* d_face_core = nullptr;  // [6][nc][CS^3]
+  double* d_face_fac = nullptr;   // [6][nc][3][CS][N]
+  int* d_face_rank = nullptr;     // [6][nc][3]
   double* Wb = nullptr;     // first-pass bases of the FP64 refinement
   double* Wkeep = nullptr;  // [nc][3][N][N] previous full eigenbases (warm start)
   bool warm = false;        // Wkeep holds real bases (after the first step)

@@ -26,7 +26,7 @@ EXPORTED = [
     "tk_ctx_create", "tk_ctx_destroy", "tk_last_error", "tk_sync", "tk_prof_enable", "tk_prof_get",
     "tk_prof_reset", "tk_prof_eig", "tk_mesh_load", "tk_mesh_destroy", "tk_state_init", "tk_state_init_batch",
     "tk_state_destroy", "tk_state_info", "tk_state_dt", "tk_state_set_chunk", "tk_state_chunk",
-    "tk_state_tune", "tk_state_use_graph", "tk_state_streams", "tk_state_rounding", "tk_state_checkpoint", "tk_state_restore", "tk_moments", "tk_step", "tk_step_async", "tk_lusgs",
+    "tk_state_tune", "tk_state_use_graph", "tk_state_streams", "tk_state_rounding", "tk_state_checkpoint", "tk_state_restore", "tk_moments", "tk_step", "tk_step_async", "tk_lusgs", "tk_state_face_rounding",
     "tk_state_ranks", "tk_state_export", "tk_round", "tk_round_tucker", "tk_round_tucker_noalloc",
     "tk_plain_init", "tk_ctx_create_ex",
     "tk_serve_create",
@@ -122,6 +122,7 @@ def lib():
             "tk_moments": [P, C.POINTER(C.c_double)],
             "tk_step": [P, C.c_int32, C.POINTER(C.c_double)],
             "tk_lusgs": [P, C.c_int32, C.POINTER(C.c_double)],
+            "tk_state_face_rounding": [P, C.c_int32],
             "tk_step_async": [P, C.c_int32],
             "tk_state_ranks": [P, C.POINTER(C.c_int32), C.POINTER(C.c_double)],
             "tk_state_export": [P, C.c_int32, C.POINTER(tk_tucker)],
@@ -398,6 +399,10 @@ class State:
         res = np.zeros(self.n_instances) if residual else None
         _check(lib().tk_lusgs(self.h, int(n), _dptr(res) if residual else None), self.ctx.h)
         return res
+
+    def face_rounding(self, on=True):
+        """tk_state_face_rounding: round each face's flux term before the sum."""
+        _check(lib().tk_state_face_rounding(self.h, 1 if on else 0), self.ctx.h)
 
     def step_async(self, n=1):
         _check(lib().tk_step_async(self.h, int(n)), self.ctx.h)
