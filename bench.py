@@ -19,7 +19,9 @@ from five further steps with every pass on one stream and HIP events around
 each launch; the plain full-tensor GPU step on the same workload; the FP64
 path timed on the same window and the mixed path's end-of-run macro error
 against it, beside the FP64 path's own spread under a 1e-7 input
-perturbation; LU-SGS iterations against explicit FP64 steps; a sampled
+perturbation; LU-SGS iterations against explicit FP64 steps; the step with
+intermediate rounding of each face's flux term against the one-rounding
+step (`face_rounding`, a few steps after a short ordinary run); a sampled
 parity check against the FP64 oracle and the oracle's own CPU throughput
 (`cpu_baseline`, one single-thread process per host core).
 """
@@ -548,6 +550,47 @@ def run_lusgs(cfg, mesh, m0, iters, cfl):
     return out
 
 
+def run_faces(cfg, mesh, m0, pre, steps):
+    """The intermediate-rounding step (each face's flux term rounded before
+    the sum) against the one-rounding step: two states advanced `pre`
+    ordinary steps, then `steps` timed steps each way; time per step, the
+    kernel families of one more step and the macro difference between the
+    two results."""
+    ctx = tk.Context(0)
+    out = {"pre_steps": pre, "steps": steps}
+    try:
+        tm = tk.Mesh(ctx, mesh)
+        finals = {}
+        for kind in ("one_rounding", "face_rounding"):
+            st = tk.State(ctx, tm, cfg, m0)
+            st.step(pre)
+            ctx.sync()
+            if kind == "face_rounding":
+                st.face_rounding(True)
+            t0 = time.perf_counter()
+            st.step(steps)
+            ctx.sync()
+            t1 = time.perf_counter()
+            finals[kind] = st.moments()
+            ctx.prof_reset()
+            ctx.prof_enable(True)
+            st.step(1)
+            ctx.prof_enable(False)
+            fams = ["moments", "expand", "gram", "eig", "project", "rround"]
+            out[kind] = {"ms_per_step": 1e3 * (t1 - t0) / steps,
+                         "kernel_ms_one_step": {f: ctx.prof_get(f)[0] for f in fams if ctx.prof_get(f)[1]}}
+            log(f"{kind}: {out[kind]['ms_per_step']:.2f} ms/step over steps {pre}..{pre + steps}")
+            st.close()
+        tm.close()
+    finally:
+        ctx.close()
+    out["cost_ratio"] = out["face_rounding"]["ms_per_step"] / out["one_rounding"]["ms_per_step"]
+    out["max_rel_macro_diff"] = macro_rel_err(finals["face_rounding"], finals["one_rounding"])
+    log(f"face rounding / one rounding: {out['cost_ratio']:.2f}x per step, macro difference "
+        f"{out['max_rel_macro_diff']:.3e} after {steps} steps (tol {cfg['tol']})")
+    return out
+
+
 def serve_run(reqs, rate, seed=5):
     """Submit requests (arrivals at t = 0 when rate is None, else Poisson with
     `rate` per second), wait for all; latency = t_done - t_arrive."""
@@ -670,6 +713,9 @@ def main():
     ap.add_argument("--no-fp64-check", action="store_true",
                     help="skip the FP64 GPU run used for the end-of-run mixed-precision error")
     ap.add_argument("--no-lusgs", action="store_true", help="skip the LU-SGS iteration timing")
+    ap.add_argument("--no-faces", action="store_true", help="skip the intermediate-rounding step timing")
+    ap.add_argument("--faces-pre", type=int, default=20)
+    ap.add_argument("--faces-steps", type=int, default=3)
     ap.add_argument("--lusgs-iters", type=int, default=4)
     ap.add_argument("--lusgs-cfl", type=float, default=4.0)
     ap.add_argument("--batch-count", type=int, default=256)
@@ -847,6 +893,9 @@ def main():
     lu = None
     if not a.no_lusgs and N <= 32 and not oblique:
         lu = run_lusgs(cfg, mesh, m0, a.lusgs_iters, a.lusgs_cfl)
+    faces = None
+    if not a.no_faces:
+        faces = run_faces(cfg, mesh, m0, a.faces_pre, a.faces_steps)
     out = {
         "metric": "Tucker S-model cell-updates/s vs plain GPU step; macro error vs the FP64 path stated",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": window, "warmup": res["pre"],
@@ -870,6 +919,7 @@ def main():
         "parity": parity,
         "end_of_run": end,
         "lusgs": lu,
+        "face_rounding": faces,
     }
     print(json.dumps(out), flush=True)
 
