@@ -94,7 +94,8 @@ enum { TK_FP64 = 0, TK_MIXED = 1 };
  * velocity method"): N uniform nodes per axis on [-xi_max, xi_max] with
  * the end points included, quadrature weight dxi^3.                       */
 typedef struct {
-  int32_t N;          /* 16, 24, 32, or 48 on the TK_MIXED path only        */
+  int32_t N;          /* 16, 24, 32 or 48 (FP64 at 48: every cell through
+                         the general fibre-pass expansion, for reference runs) */
   double xi_max;
   double R_g, m;      /* gas constant, molecular mass                      */
   double Pr;          /* Prandtl number (2/3 for a monatomic gas)          */

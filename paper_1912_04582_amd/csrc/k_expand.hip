@@ -1000,7 +1000,9 @@ template <int N, int BLOCK, typename T>
 __device__ inline void ob_tables(const DevState& d, int c, T* sxi, T* sd, double (&nrm)[kSlots][3]) {
   const int tid = threadIdx.x;
   const InstParams P = d.ip[d.inst[c]];
-  if (tid < kSlots * 3) nrm[tid / 3][tid % 3] = d.slot_nrm[(size_t)kSlots * 3 * c + tid];
+  // outward normals (the table exists only on states with oblique faces;
+  // they are read for oblique slots only)
+  if (d.slot_nrm && tid < kSlots * 3) nrm[tid / 3][tid % 3] = d.slot_nrm[(size_t)kSlots * 3 * c + tid];
   for (int i = tid; i < N; i += BLOCK) {
     const double x = P.xi_min + i * P.dxi;
     sxi[i] = (T)x;
@@ -1705,6 +1707,7 @@ hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixe
         case 16: return launch_expand_obl_t<16, double>(d, c0, count, X, list, list_n, s);
         case 24: return launch_expand_obl_t<24, double>(d, c0, count, X, list, list_n, s);
         case 32: return launch_expand_obl_t<32, double>(d, c0, count, X, list, list_n, s);
+        case 48: return launch_expand_obl_t<48, double>(d, c0, count, X, list, list_n, s);
       }
     }
     return hipErrorInvalidValue;
@@ -1721,6 +1724,9 @@ hipError_t launch_expand(const DevState& d, int c0, int count, void* X, int mixe
       case 16: return launch_expand_t<16, double>(d, c0, count, X, list, list_n, s);
       case 24: return launch_expand_t<24, double>(d, c0, count, X, list, list_n, s);
       case 32: return launch_expand_t<32, double>(d, c0, count, X, list, list_n, s);
+      // the axis-face kernels' FP64 layouts do not fit the LDS at N = 48: the
+      // general path of oblique meshes (separable tables for axis faces)
+      case 48: return launch_expand_obl_t<48, double>(d, c0, count, X, list, list_n, s);
     }
   }
   return hipErrorInvalidValue;
@@ -1741,6 +1747,7 @@ hipError_t launch_face_term(const DevState& d, int c0, int count, void* X, int m
       case 16: return launch_face_term_t<16, double>(d, c0, count, X, slot, s);
       case 24: return launch_face_term_t<24, double>(d, c0, count, X, slot, s);
       case 32: return launch_face_term_t<32, double>(d, c0, count, X, slot, s);
+      case 48: return launch_face_term_t<48, double>(d, c0, count, X, slot, s);
     }
   }
   return hipErrorInvalidValue;
@@ -1761,6 +1768,7 @@ hipError_t launch_face_sum(const DevState& d, const FaceStates& fs, int c0, int 
       case 16: return launch_face_sum_t<16, double>(d, fs, c0, count, X, s);
       case 24: return launch_face_sum_t<24, double>(d, fs, c0, count, X, s);
       case 32: return launch_face_sum_t<32, double>(d, fs, c0, count, X, s);
+      case 48: return launch_face_sum_t<48, double>(d, fs, c0, count, X, s);
     }
   }
   return hipErrorInvalidValue;

@@ -218,7 +218,7 @@ constexpr size_t gram_lds_bytes() {
 template <int N, typename T>
 __global__ __launch_bounds__(256) void k_gram_rot(const T* X, const double* Wb, double* G2, int c0,
                                                    const int* cells_n) {
-  constexpr int CH = 64;
+  constexpr int CH = N >= 48 ? 32 : 64;  // keeps the static LDS within 64 KB at N = 48
   constexpr int PER = (N * N + 255) / 256;
   __shared__ double W[N * N];
   __shared__ double Ac[N * (CH + 1)];
@@ -281,6 +281,7 @@ hipError_t launch_gram_rot(int N, int count, const void* X, int mixed, const dou
       case 16: hipLaunchKernelGGL((k_gram_rot<16, float>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
       case 24: hipLaunchKernelGGL((k_gram_rot<24, float>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
       case 32: hipLaunchKernelGGL((k_gram_rot<32, float>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
+      case 48: hipLaunchKernelGGL((k_gram_rot<48, float>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -289,6 +290,7 @@ hipError_t launch_gram_rot(int N, int count, const void* X, int mixed, const dou
       case 16: hipLaunchKernelGGL((k_gram_rot<16, double>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
       case 24: hipLaunchKernelGGL((k_gram_rot<24, double>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
       case 32: hipLaunchKernelGGL((k_gram_rot<32, double>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
+      case 48: hipLaunchKernelGGL((k_gram_rot<48, double>), grid, blk, 0, s, x, W, G2, c0, cells_n); break;
       default: return hipErrorInvalidValue;
     }
   }

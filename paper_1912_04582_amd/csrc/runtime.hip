@@ -261,8 +261,6 @@ static tk_status check_params(tk_ctx* ctx, const tk_params* p) {
     return ctx_fail(ctx, TK_EINVAL, "params: xi_max, R_g, m, Kn, cfl, Pr must be positive and tol >= 0");
   if (p->precision != TK_FP64 && p->precision != TK_MIXED)
     return ctx_fail(ctx, TK_EINVAL, "params: precision must be TK_FP64 or TK_MIXED");
-  if (p->precision == TK_FP64 && p->N == 48)
-    return ctx_fail(ctx, TK_EINVAL, "params: the FP64 path supports N <= 32");
   return TK_OK;
 }
 

@@ -78,6 +78,41 @@ def test_jittered_box_full_size_cones():
     assert err < 1e-5, err
 
 
+@pytest.mark.parametrize("kind", ["channel", "jittered"])
+def test_fp64_at_n48_matches_oracle(kind):
+    """The FP64 path at N = 48 (the grid of the jittered-box workload):
+    every cell of a small channel (axis faces, all boundary kinds) or
+    jittered box (oblique faces) after 2 steps, against the oracle."""
+    if kind == "channel":
+        m = synth.channel_with_obstacle(nx=6, ny=3, nz=3, h=0.25, obstacle=((2, 3), (1, 2), (1, 2)),
+                                        inflow=(1.0, (0.9, 0.0, 0.0), 1.0), Tw=1.4)
+    else:
+        m = synth.jittered_box(3, 3, 2, 1 / 3, seed=11)
+    cfg = dict(N=48, xi_max=7.0, cap=8, tol=1e-5, cfl=0.5, Pr=2 / 3, omega=0.5, Kn=0.1, Rg=0.5, m=1.0, seed=13,
+               init="random", precision="fp64")
+    m0 = synth.initial_macros(cfg, m)
+    steps = 2
+    ctx = tk.Context(0)
+    try:
+        tm = tk.Mesh(ctx, m)
+        st = tk.State(ctx, tm, cfg, m0)
+        st.set_chunk(7)  # several passes and a ragged last one
+        st.step(steps)
+        got, ranks = st.moments(), st.ranks()[0]
+        st.close(); tm.close()
+    finally:
+        ctx.close()
+    S = fv.Setup(m, cfg, m0)
+    ref = td.run(S, m0, steps)
+    oranks = np.array([ref[i].ranks for i in range(m["n_cells"])])
+    ref = np.array([td.macros_of(S, ref[i]) for i in range(m["n_cells"])])
+    err, _ = macro_rel_err(got, ref)
+    print(f"FP64 N=48 {kind}, {steps} steps: max rel macro err {err:.3e}, rank mismatches "
+          f"{(ranks != oranks).any(1).sum()}")
+    assert err < 1e-10, err
+    assert (ranks == oranks).all()
+
+
 @pytest.mark.parametrize("N,precision,bar", [(16, "mixed", 1e-5), (24, "mixed", 1e-5), (32, "mixed", 1e-5),
                                              (24, "fp64", 1e-10)])
 def test_batch_per_grid_matches_oracle(N, precision, bar):

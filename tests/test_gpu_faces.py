@@ -68,6 +68,7 @@ CASES = [
     ("jittered", 24, 6, 1e-4, "fp64", 2, 11, 1e-10),
     ("channel", 24, 8, 1e-4, "mixed", 2, None, 1e-5),
     ("jittered", 16, 6, 1e-4, "mixed", 2, None, 1e-5),
+    ("jittered", 48, 6, 1e-4, "fp64", 1, None, 1e-10),
 ]
 
 

@@ -291,7 +291,7 @@ def test_invalid_arguments_rejected(ctx):
     m, cfg = small_channel()
     m0 = synth.initial_macros(cfg, m)
     mesh = tk.Mesh(ctx, m)
-    for bad in (dict(N=20), dict(cap=17), dict(cap=0), dict(tol=-1.0), dict(precision="fp64", N=48)):
+    for bad in (dict(N=20), dict(cap=17), dict(cap=0), dict(tol=-1.0), dict(N=64)):
         with pytest.raises(tk.TkError) as ei:
             tk.State(ctx, mesh, dict(cfg, **bad), m0)
         assert ei.value.status == tk.TK_EINVAL
