@@ -1211,6 +1211,35 @@ __global__ __launch_bounds__(BLOCK) void k_expand_obl(DevState d, int c0, T* X, 
   ob_fast<N, BLOCK, T>(d, c, X + (size_t)blockIdx.x * N * N * N, sxi, sd, sd + 3 * N, s_tab, s_nrm);
 }
 
+// The one-stage path with a larger LDS budget (one workgroup per CU) over the
+// cells an earlier launch listed (pass-local indices in / in_n); the cells
+// that still do not fit go to list / list_n.
+template <int N, int BLOCK, typename T>
+__global__ __launch_bounds__(BLOCK) void k_expand_obl_listed(DevState d, int c0, T* X, int lds_floats,
+                                                             const int* in, const int* in_n, int* list,
+                                                             int* list_n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  T* sxi = smem;      // N
+  T* sd = sxi + N;    // 3 N
+  __shared__ double s_nrm[kSlots][3];
+  __shared__ ObTab s_tab;
+  const int n = *in_n;
+  for (int b = blockIdx.x; b < n; b += gridDim.x) {
+    const int bi = in[b];
+    const int c = d.cells ? d.cells[c0 + bi] : c0 + bi;
+    ob_tables<N, BLOCK, T>(d, c, sxi, sd, s_nrm);
+    if (threadIdx.x == 0) ob_table(d, c, N, s_tab);
+    __syncthreads();
+    if (s_tab.need > lds_floats - 4 * N) {
+      if (threadIdx.x == 0) list[atomicAdd(list_n, 1)] = bi;
+    } else {
+      ob_fast<N, BLOCK, T>(d, c, X + (size_t)bi * N * N * N, sxi, sd, sd + 3 * N, s_tab, s_nrm);
+    }
+    __syncthreads();  // the tables are rewritten for the next cell
+  }
+}
+
 template <int N, int BLOCK, typename T>
 __global__ __launch_bounds__(BLOCK) void k_expand_obl_general(DevState d, int c0, T* X, const int* list,
                                                               const int* list_n) {
@@ -1428,13 +1457,24 @@ hipError_t launch_expand_obl_t(const DevState& d, int c0, int count, void* X, in
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, list_n);
   hipLaunchKernelGGL(kf, dim3(count), dim3(B), fast, s, d, c0, (T*)X, (int)(fast / sizeof(T)), list, list_n);
-  // the listed cells, any ranks
+  // the listed cells through the one-stage path with one workgroup's worth of
+  // LDS per CU (list entries from `count` on, second counter), then the
+  // cells left, any ranks, through the restaging path
+  int* list2 = list + count;
+  int* list2_n = list_n + 1;
+  const size_t big = (size_t)150 * 1024;
+  auto kb = k_expand_obl_listed<N, B, T>;
+  e = hipFuncSetAttribute((const void*)kb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)big);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, list2_n);
+  hipLaunchKernelGGL(kb, dim3(count < 512 ? count : 512), dim3(B), big, s, d, c0, (T*)X, (int)(big / sizeof(T)),
+                     (const int*)list, (const int*)list_n, list2, list2_n);
   const int CSL = d.CS > kEstCap ? d.CS : kEstCap;
   const size_t slow = sizeof(T) * (4 * N + 3 * CSL * N + CSL * CSL * CSL + KC * CSL * N + KC * B);
   auto ks = k_expand_obl_general<N, B, T>;
   e = hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)slow);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ks, dim3(count < 1024 ? count : 1024), dim3(B), slow, s, d, c0, (T*)X, list, list_n);
+  hipLaunchKernelGGL(ks, dim3(count < 1024 ? count : 1024), dim3(B), slow, s, d, c0, (T*)X, list2, list2_n);
   return hipGetLastError();
 }
 

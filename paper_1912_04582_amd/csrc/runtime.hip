@@ -360,7 +360,7 @@ size_t state_bytes_estimate(int nc, const tk_params& p, bool plain, int chunk) {
     b += 2 * (size_t)nc * (CS * CS * CS + 3 * CS * N) * 8 + 2 * (size_t)nc * 3 * 4;
     b += (size_t)nc * 3 * N * N * 8;                      // warm-start eigenbases
     b += (size_t)nc * (4 + 4 + 12);                       // rounding lists, basis validity
-    b += ch * (N * N * N * tsz + 3 * N * N * 8);          // X and Gram workspaces
+    b += ch * (N * N * N * tsz + 3 * N * N * 8 + 8);      // X, Gram workspaces, the expansion's cell lists
     if (p.precision == TK_FP64) b += ch * 3 * N * N * 8;  // first-pass bases
     b += (size_t)nc * kSlots * (3 * 8 + 4);               // oblique slots
     b += (size_t)nc * 3 * (kEstCap * kEstCap * kEstCap + 3 * kEstCap * N) * 8 / 2;  // estimates
@@ -557,8 +557,10 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     ALLOC(G, double, (size_t)S->chunk * 3 * N * N);
     // cells of a pass left to a second expansion launch (oblique faces or
     // ranks beyond the small LDS layout)
-    ALLOC(ob_list, int, (size_t)S->chunk);
-    ALLOC(ob_n, int, 1);
+    // two lists of a pass's cells and their counters (the oblique expansion
+    // hands cells on twice)
+    ALLOC(ob_list, int, 2 * (size_t)S->chunk);
+    ALLOC(ob_n, int, 2);
     if (!S->mixed) ALLOC(Wb, double, (size_t)S->chunk * 3 * N * N);
     ALLOC(Wkeep, double, (size_t)nc * 3 * N * N);
     ALLOC(d_wvalid, int, (size_t)nc * 3);
@@ -580,14 +582,14 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     // optional second workspace: only if it fits what the budget leaves
     // (with a margin), so that no error is recorded when it does not
     const size_t ch = (size_t)S->chunk;
-    const size_t need = ch * N * N * N * tsz + ch * 3 * N * N * 8 * (S->mixed ? 1 : 2) + ch * 4 + 4096;
+    const size_t need = ch * N * N * N * tsz + ch * 3 * N * N * 8 * (S->mixed ? 1 : 2) + 2 * ch * 4 + 4096;
     if (nc > 1 && !served && ctx->used + need + (64u << 20) <= ctx->budget) {
       tk_status s2 = TK_OK;
       S->X2 = st_alloc(S, ch * N * N * N * tsz, &s2);
       if (S->X2) S->G2 = (double*)st_alloc(S, ch * 3 * N * N * 8, &s2);
       if (S->G2 && !S->mixed) S->Wb2 = (double*)st_alloc(S, ch * 3 * N * N * 8, &s2);
-      if (S->G2 && (S->mixed || S->Wb2)) S->ob_list2 = (int*)st_alloc(S, ch * 4, &s2);
-      if (S->ob_list2) S->ob_n2 = (int*)st_alloc(S, 4, &s2);
+      if (S->G2 && (S->mixed || S->Wb2)) S->ob_list2 = (int*)st_alloc(S, 2 * ch * 4, &s2);
+      if (S->ob_list2) S->ob_n2 = (int*)st_alloc(S, 2 * 4, &s2);
       if (S->ob_n2 && hipStreamCreate(&S->q2) != hipSuccess) S->q2 = nullptr;
       if (S->q2 && (hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming) != hipSuccess ||
                     hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming) != hipSuccess)) {
