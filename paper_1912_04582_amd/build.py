@@ -1,7 +1,8 @@
 """Build libtk.so (the HIP library behind include/tk.h) for gfx950, in tree.
 
-Every translation unit is compiled with hipcc for gfx950 only, packed FP32
-instructions disabled, then linked into paper_1912_04582_amd/libtk.so.
+Every translation unit (the HIP sources and the host-only checks in host.cpp)
+is compiled with hipcc for gfx950 only, packed FP32 instructions disabled,
+then linked into paper_1912_04582_amd/libtk.so.
 Usage: python -m paper_1912_04582_amd.build [-j JOBS] [--debug]
 """
 
@@ -28,7 +29,7 @@ FLAGS = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def hipcc():

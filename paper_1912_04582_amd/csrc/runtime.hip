@@ -65,13 +65,6 @@ tk_status ctx_fail(tk_ctx* ctx, tk_status st, const std::string& msg) {
   return st;
 }
 
-int face_axis(const double* e) {
-  int axis = -1, nz = 0;
-  for (int a = 0; a < 3; ++a)
-    if (e[a] != 0.0) { axis = a; ++nz; }
-  return (nz == 1 && std::fabs(std::fabs(e[axis]) - 1.0) <= 1e-12) ? axis : -1;
-}
-
 tk_status ctx_hip(tk_ctx* ctx, hipError_t e, const char* what) {
   if (e == hipSuccess) return TK_OK;
   return ctx_fail(ctx, e == hipErrorOutOfMemory ? TK_ENOMEM : TK_EDEVICE,
@@ -160,89 +153,9 @@ void prof_harvest(tk_ctx* ctx) {
 // mesh
 
 static tk_status mesh_build(tk_ctx* ctx, const tk_mesh_desc* d, tk_mesh* m) {
-  if (!d || d->n_cells <= 0 || d->n_faces <= 0 || !d->face_left || !d->face_right || !d->face_normal ||
-      !d->face_area || !d->cell_volume || d->n_bc < 0 || (d->n_bc > 0 && !d->bc))
-    return ctx_fail(ctx, TK_EINVAL, "mesh: missing arrays or empty mesh");
-  const int nc = d->n_cells, nf = d->n_faces;
-  m->n_cells = nc;
-  m->n_faces = nf;
-  m->volume.assign(d->cell_volume, d->cell_volume + nc);
-  m->bc.assign(d->bc, d->bc + d->n_bc);
-  for (int i = 0; i < nc; ++i)
-    if (!(m->volume[i] > 0.0) || !std::isfinite(m->volume[i]))
-      return ctx_fail(ctx, TK_EINVAL, "mesh: non-positive cell volume at cell " + std::to_string(i));
-  for (const tk_bc& b : m->bc)
-    if (b.kind < TK_BC_SYM || b.kind > TK_BC_WALL) return ctx_fail(ctx, TK_EINVAL, "mesh: unknown bc kind");
-  m->slot_nb.assign((size_t)nc * kSlots, -1);
-  m->slot_kind.assign((size_t)nc * kSlots, SK_NONE);
-  m->slot_axis.assign((size_t)nc * kSlots, 0);
-  m->slot_sig.assign((size_t)nc * kSlots, 1);
-  m->slot_area.assign((size_t)nc * kSlots, 0.0);
-  m->slot_l1.assign((size_t)nc * kSlots, 0.0);
-  m->slot_nrm.assign((size_t)nc * kSlots * 3, 0.0);
-  m->slot_face.assign((size_t)nc * kSlots, -1);
-  m->face_normal.assign(d->face_normal, d->face_normal + 3 * (size_t)nf);
-  m->oblique = false;
-  std::vector<int> cnt(nc, 0);
-  int cur_face = -1;
-  std::vector<double> close((size_t)nc * 3, 0.0), asum(nc, 0.0);
-  auto add_slot = [&](int c, int nb, int8_t kind, const double* e, double sgn, double A) -> tk_status {
-    if (cnt[c] >= kSlots) return ctx_fail(ctx, TK_EINVAL, "mesh: cell " + std::to_string(c) + " has more than 6 faces");
-    int axis = face_axis(e);
-    const bool on_axis = axis >= 0;
-    if (!on_axis) {
-      axis = -1;
-      if (kind == SK_SYM || kind == SK_WALL)
-        return ctx_fail(ctx, TK_EINVAL, "mesh: symmetry and wall faces must lie on coordinate-axis planes");
-      m->oblique = true;
-    }
-    const int s = cnt[c]++;
-    const size_t k = (size_t)c * kSlots + s;
-    m->slot_nb[k] = nb;
-    m->slot_kind[k] = kind;
-    m->slot_axis[k] = (int8_t)axis;
-    m->slot_sig[k] = (int8_t)((on_axis ? sgn * e[axis] : sgn) > 0 ? 1 : -1);
-    for (int a = 0; a < 3; ++a) m->slot_nrm[3 * k + a] = sgn * e[a];
-    m->slot_face[k] = cur_face;
-    m->slot_area[k] = A;
-    m->slot_l1[k] = A * (std::fabs(e[0]) + std::fabs(e[1]) + std::fabs(e[2]));
-    for (int a = 0; a < 3; ++a) close[3 * c + a] += sgn * A * e[a];
-    asum[c] += A;
-    return TK_OK;
-  };
-  for (int j = 0; j < nf; ++j) {
-    cur_face = j;
-    const int L = d->face_left[j], R = d->face_right[j];
-    const double* e = d->face_normal + 3 * (size_t)j;
-    const double A = d->face_area[j];
-    if (L < 0 || L >= nc) return ctx_fail(ctx, TK_EINVAL, "mesh: face_left out of range at face " + std::to_string(j));
-    if (!(A > 0.0) || !std::isfinite(A)) return ctx_fail(ctx, TK_EINVAL, "mesh: bad face area");
-    const double en = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-    if (std::fabs(en - 1.0) > 1e-10) return ctx_fail(ctx, TK_EINVAL, "mesh: face normal is not unit length");
-    tk_status st;
-    if (R >= 0) {
-      if (R >= nc || R == L) return ctx_fail(ctx, TK_EINVAL, "mesh: face_right out of range");
-      if ((st = add_slot(L, R, SK_INTERIOR, e, 1.0, A)) != TK_OK) return st;
-      if ((st = add_slot(R, L, SK_INTERIOR, e, -1.0, A)) != TK_OK) return st;
-    } else {
-      const int b = -R - 1;
-      if (b >= (int)m->bc.size()) return ctx_fail(ctx, TK_EINVAL, "mesh: boundary index out of range");
-      int8_t kind = SK_NONE;
-      switch (m->bc[b].kind) {
-        case TK_BC_SYM: kind = SK_SYM; break;
-        case TK_BC_INFLOW: kind = SK_INFLOW; break;
-        case TK_BC_OUTFLOW: kind = SK_OUTFLOW; break;
-        case TK_BC_WALL: kind = SK_WALL; break;
-      }
-      if ((st = add_slot(L, b, kind, e, 1.0, A)) != TK_OK) return st;
-    }
-  }
-  for (int c = 0; c < nc; ++c) {
-    const double r = std::sqrt(close[3 * c] * close[3 * c] + close[3 * c + 1] * close[3 * c + 1] +
-                               close[3 * c + 2] * close[3 * c + 2]);
-    if (r > 1e-12 * asum[c]) return ctx_fail(ctx, TK_EINVAL, "mesh: cell " + std::to_string(c) + " is not closed");
-  }
-  return TK_OK;
+  std::string err;
+  const tk_status s = tk::mesh_build_host(d, m, &err);
+  return s == TK_OK ? TK_OK : ctx_fail(ctx, s, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -1473,11 +1386,6 @@ tk_status tk_state_dt(const tk_state* st, int32_t inst, double* dt) {
 // ---- checkpoints -------------------------------------------------------------
 namespace {
 
-struct CkptHeader {
-  char magic[8];  // "TKCKPT2"
-  int32_t N, CS, nc, ninst, mixed, plain, warm, pad;
-};
-
 struct CkptLayout {
   size_t ip, core, fac, rank, wkeep, wvalid, f, total;
 };
@@ -1553,14 +1461,15 @@ tk_status tk_state_restore(tk_state* st, const void* buf, size_t bytes) {
   std::lock_guard<std::recursive_mutex> g(ctx->mu);
   const CkptLayout L = ckpt_layout(st);
   const unsigned char* b = static_cast<const unsigned char*>(buf);
-  if (bytes < sizeof(CkptHeader)) return ctx_fail(ctx, TK_EINVAL, "restore: buffer too small");
-  CkptHeader h;
-  std::memcpy(&h, b, sizeof(h));
-  if (std::memcmp(h.magic, "TKCKPT2", 8) != 0) return ctx_fail(ctx, TK_EINVAL, "restore: not a checkpoint");
-  if (h.N != st->N || h.CS != st->CS || h.nc != st->nc || h.ninst != st->ninst || h.mixed != (st->mixed ? 1 : 0) ||
-      h.plain != (st->plain ? 1 : 0))
-    return ctx_fail(ctx, TK_EINVAL, "restore: checkpoint of a different state shape");
-  if (bytes < L.total) return ctx_fail(ctx, TK_EINVAL, "restore: buffer too small");
+  CkptHeader want{};
+  want.N = st->N;
+  want.CS = st->CS;
+  want.nc = st->nc;
+  want.ninst = st->ninst;
+  want.mixed = st->mixed ? 1 : 0;
+  want.plain = st->plain ? 1 : 0;
+  std::string err;
+  if (ckpt_check_header(buf, bytes, want, L.total, &err) != TK_OK) return ctx_fail(ctx, TK_EINVAL, err);
   std::vector<tk::InstParams> ip(st->ninst);
   std::memcpy(ip.data(), b + L.ip, sizeof(tk::InstParams) * st->ninst);
   for (int k = 0; k < st->ninst; ++k)
@@ -1568,6 +1477,14 @@ tk_status tk_state_restore(tk_state* st, const void* buf, size_t bytes) {
       return ctx_fail(ctx, TK_EINVAL, "restore: checkpoint of different instance parameters");
   hipStream_t q = ctx->stream;
   const size_t nc = st->nc, N = st->N, CS = st->CS;
+  // ranks index the factor and core layouts in every kernel: a buffer with
+  // ranks outside 1..CS is refused before anything reaches the device
+  std::vector<int> rk;
+  if (!st->plain) {
+    rk.resize(nc * 3);
+    std::memcpy(rk.data(), b + L.rank, nc * 3 * sizeof(int));
+    if (ckpt_check_ranks(rk.data(), rk.size(), st->CS, &err) != TK_OK) return ctx_fail(ctx, TK_EINVAL, err);
+  }
   hipError_t e = hipStreamSynchronize(q);
   if (e == hipSuccess) e = hipMemcpy(st->d_ip, ip.data(), sizeof(tk::InstParams) * st->ninst, hipMemcpyHostToDevice);
   if (st->plain) {
@@ -1577,7 +1494,7 @@ tk_status tk_state_restore(tk_state* st, const void* buf, size_t bytes) {
       e = hipMemcpy(st->core[st->cur], b + L.core, nc * CS * CS * CS * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(st->fac[st->cur], b + L.fac, nc * 3 * CS * N * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(st->rank[st->cur], b + L.rank, nc * 3 * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(st->rank[st->cur], rk.data(), nc * 3 * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(st->Wkeep, b + L.wkeep, nc * 3 * N * N * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(st->d_wvalid, b + L.wvalid, nc * 3 * sizeof(int), hipMemcpyHostToDevice);
@@ -1601,6 +1518,8 @@ tk_status tk_state_restore(tk_state* st, const void* buf, size_t bytes) {
     if (e != hipSuccess) return ctx_hip(ctx, e, "restore face coefficients");
   }
   st->ip_host = ip;
+  CkptHeader h;
+  std::memcpy(&h, b, sizeof(h));
   st->warm = h.warm != 0;
   return TK_OK;
 }

@@ -10,23 +10,12 @@
 #include <vector>
 
 #include "tk.h"
+#include "tk_host.h"
 
 namespace tk {
 
-constexpr int kMaxCap = 16;  // largest Tucker rank per mode
-constexpr int kSlots = 6;    // faces per hexahedral cell
 constexpr int kEstCap = 6;   // mode ranks of the |xi.e| estimate on oblique faces
 constexpr double kEstDrop = 1e-14;  // estimate: drop singular values <= kEstDrop sigma_1
-
-// Kind of the cell on the far side of a face slot.
-enum SlotKind : int8_t {
-  SK_NONE = -1,     // unused slot (cell with fewer than 6 faces)
-  SK_INTERIOR = 0,  // another cell of the same state
-  SK_INFLOW = 1,    // free-stream Maxwellian
-  SK_OUTFLOW = 2,   // zero-gradient: the cell itself
-  SK_SYM = 3,       // symmetry plane: the cell with one velocity axis reversed
-  SK_WALL = 4,      // diffuse wall: n_w times the unit wall Maxwellian
-};
 
 // Per-instance parameters, device resident (one entry per instance).
 struct InstParams {

@@ -34,24 +34,6 @@ struct tk_ctx {
   std::map<std::string, int> tuned_chunk;
 };
 
-struct tk_mesh {
-  tk_ctx* ctx = nullptr;
-  int n_cells = 0, n_faces = 0;
-  std::vector<double> volume;
-  std::vector<tk_bc> bc;
-  // per cell, kSlots face slots
-  std::vector<int> slot_nb;        // neighbour cell or local bc index
-  std::vector<int8_t> slot_kind;   // tk::SlotKind
-  std::vector<int8_t> slot_axis;
-  std::vector<int8_t> slot_sig;    // outward orientation along the axis
-  std::vector<double> slot_area;
-  std::vector<double> slot_l1;     // A ||e||_1
-  std::vector<double> slot_nrm;    // [nc][6][3] outward unit normal
-  std::vector<int> slot_face;      // face index of the slot
-  bool oblique = false;            // some face normal is off the coordinate axes
-  std::vector<double> face_normal; // [n_faces][3]
-};
-
 struct tk_state {
   tk_ctx* ctx = nullptr;
   int N = 0, CS = 0;
@@ -168,8 +150,6 @@ struct tk_state {
 // shared helpers (runtime.hip)
 tk_status ctx_fail(tk_ctx* ctx, tk_status st, const std::string& msg);
 tk_status ctx_hip(tk_ctx* ctx, hipError_t e, const char* what);
-// the coordinate axis a unit face normal lies on, or -1 (an oblique face)
-int face_axis(const double* e);
 void* ctx_alloc(tk_ctx* ctx, size_t bytes, tk_status* st);
 void ctx_free(tk_ctx* ctx, void* p);
 tk_status state_steps(tk_state* st, int nsteps, double* residual, bool wait, bool lusgs = false);
