@@ -260,6 +260,26 @@ def test_checkpoint_restore_continues_bit_for_bit(ctx, plain):
     assert ei.value.status == tk.TK_EINVAL
     with pytest.raises(tk.TkError):
         c.restore(ck[:100])
+    if not plain:
+        # ranks outside 1..CS in the buffer are refused before they reach
+        # the device, and the state still takes the intact checkpoint
+        rb = a.ranks()[0]
+        b2 = tk.State(ctx, mesh, cfg, m0)
+        b2.step(5)
+        ck5 = b2.checkpoint()
+        pat = b2.ranks()[0].astype(np.int32).tobytes()
+        raw = ck5.tobytes()
+        off = raw.find(pat)  # the rank section precedes the other int sections
+        assert off > 0
+        bad = ck5.copy()
+        bad[off:off + 4] = np.frombuffer(np.int32(99).tobytes(), dtype=np.uint8)
+        with pytest.raises(tk.TkError) as ei:
+            b2.restore(bad)
+        assert ei.value.status == tk.TK_EINVAL
+        b2.restore(ck5)
+        b2.step(5)
+        assert np.array_equal(b2.ranks()[0], rb)
+        b2.close()
     for s in (a, b, c):
         s.close()
     mesh.close()
