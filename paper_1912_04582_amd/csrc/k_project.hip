@@ -14,7 +14,7 @@ constexpr int kProjThreads = 256;
 template <int N, typename T>
 __global__ __launch_bounds__(kProjThreads) void k_project(const T* X, int c0, int CS, const double* fac_n,
                                                          const int* rank_n, double* core_n, const int* cells,
-                                                         const int* cells_n) {
+                                                         const int* cells_n, int lo) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sS = reinterpret_cast<double*>(smem_raw);  // N*N slice
   double* sW = sS + N * N;                             // 3 * CS * N
@@ -25,6 +25,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project(const T* X, int c0, in
   const int cell = cells ? cells[c0 + cl] : c0 + cl;
   const int tid = threadIdx.x;
   const int r1 = rank_n[3 * cell], r2 = rank_n[3 * cell + 1], r3 = rank_n[3 * cell + 2];
+  // cells whose larger rank of modes 1 and 2 is <= lo went through k_project_fib
+  if ((r1 > r2 ? r1 : r2) <= lo) return;
   for (int o = tid; o < 3 * CS * N; o += kProjThreads)
     sW[o] = fac_n[(size_t)cell * 3 * CS * N + o];
   constexpr int MAXC = kMaxCap * kMaxCap * kMaxCap / kProjThreads;
@@ -149,28 +151,43 @@ size_t project_fib_bytes(int CS, int cap) {
 
 // rank tiers of the projection launches: (0, 6], (6, 9], (9, cap]
 constexpr int kProjTier[2] = {6, 9};
+// largest LDS layout of k_project_fib (one workgroup per CU); the tiers
+// above it (large N and caps) go through the slice kernel
+constexpr size_t kProjFibMax = (size_t)150 * 1024;
 
 template <int N, typename T>
 hipError_t launch_project_t(int count, const void* X, int c0, int CS, const double* fac_n, const int* rank_n,
                             double* core_n, hipStream_t s, const int* cells, const int* cells_n) {
-  const size_t shf = project_fib_bytes<N, T>(CS, CS);
-  if (shf <= 96 * 1024) {
-    auto k = k_project_fib<N, T>;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shf);
-    if (e != hipSuccess) return e;
-    int lo = 0;
-    for (int t = 0; t <= 2 && lo < CS; ++t) {
-      const int hi = (t < 2 && kProjTier[t] < CS) ? kProjTier[t] : CS;
-      const size_t sh = project_fib_bytes<N, T>(CS, hi);
-      hipLaunchKernelGGL(k, dim3(count), dim3(kProjThreads), sh, s, (const T*)X, c0, CS, fac_n, rank_n, core_n, hi,
-                         lo, hi, cells, cells_n);
-      lo = hi;
+  auto k = k_project_fib<N, T>;
+  int lo = 0;
+  bool attr = false;
+  for (int t = 0; t <= 2 && lo < CS; ++t) {
+    const int hi = (t < 2 && kProjTier[t] < CS) ? kProjTier[t] : CS;
+    const size_t sh = project_fib_bytes<N, T>(CS, hi);
+    if (sh > kProjFibMax) break;
+    if (!attr) {
+      // the largest layout this call launches
+      size_t top = sh;
+      for (int u = t + 1, l2 = hi; u <= 2 && l2 < CS; ++u) {
+        const int h2 = (u < 2 && kProjTier[u] < CS) ? kProjTier[u] : CS;
+        const size_t s2 = project_fib_bytes<N, T>(CS, h2);
+        if (s2 > kProjFibMax) break;
+        top = s2;
+        l2 = h2;
+      }
+      const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)top);
+      if (e != hipSuccess) return e;
+      attr = true;
     }
-    return hipGetLastError();
+    hipLaunchKernelGGL(k, dim3(count), dim3(kProjThreads), sh, s, (const T*)X, c0, CS, fac_n, rank_n, core_n, hi,
+                       lo, hi, cells, cells_n);
+    lo = hi;
   }
-  const size_t sh = sizeof(double) * (N * N + 3 * CS * N + CS * N + CS * CS);
-  hipLaunchKernelGGL((k_project<N, T>), dim3(count), dim3(kProjThreads), sh, s, (const T*)X, c0, CS, fac_n,
-                     rank_n, core_n, cells, cells_n);
+  if (lo < CS) {
+    const size_t sh = sizeof(double) * (N * N + 3 * CS * N + CS * N + CS * CS);
+    hipLaunchKernelGGL((k_project<N, T>), dim3(count), dim3(kProjThreads), sh, s, (const T*)X, c0, CS, fac_n,
+                       rank_n, core_n, cells, cells_n, lo);
+  }
   return hipGetLastError();
 }
 
