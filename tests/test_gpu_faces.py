@@ -119,3 +119,28 @@ def test_face_rounding_refuses_plain_states(ctx):
         pl.face_rounding(True)
     pl.close()
     tm.close()
+
+
+def test_face_rounding_batch_matches_oracle(ctx):
+    # two instances of one state with their own tolerance and cap: every
+    # face-term rounding takes its instance's
+    items = []
+    for k, (mesh, cap, tol) in enumerate([(channel(), 6, 1e-4), (jittered(), 5, 1e-3)]):
+        cfg, m0 = case(mesh, 16, cap, tol, "fp64", seed=20 + k)
+        items.append((mesh, cfg, m0))
+    meshes = [tk.Mesh(ctx, m) for m, _, _ in items]
+    st = tk.State(ctx, meshes, [c for _, c, _ in items], [m0 for _, _, m0 in items])
+    st.face_rounding(True)
+    st.step(2)
+    got, ranks = st.moments(), st.ranks()[0]
+    st.close()
+    for mm in meshes:
+        mm.close()
+    off = 0
+    for mesh, cfg, m0 in items:
+        n = mesh["n_cells"]
+        ref, oranks = oracle_run(mesh, cfg, m0, [True, True])
+        err, _ = macro_rel_err(got[off:off + n], ref)
+        assert err < 1e-10, err
+        assert (ranks[off:off + n] == oranks).all()
+        off += n
