@@ -1533,7 +1533,7 @@ hipError_t launch_expand_t(const DevState& d, int c0, int count, void* X, int* l
     const size_t b = 3 * LS * N + ((LS * LS * LS + 1) & ~1) + (MF ? 0 : LS * LS * N);
     return sizeof(T) * (3 * N + 3 * LS * N + 64 + 2 * b + (MF ? (B / 64) * 2 * LS * LS : 0));
   };
-  if (MF && CS > kExpRB && list && list_n) {
+  if (CS > kExpRB && list && list_n && pipe_lds(CS) <= (size_t)150 * 1024) {
     // cells whose sources all have ranks <= kExpRB: a small LDS layout, three
     // workgroups per CU; the rest through the full layout, from the list
     constexpr int RB = kExpRB;
