@@ -468,10 +468,9 @@ static tk_status state_create(tk_ctx* ctx, int count, const tk_mesh* const* mesh
     S->X = st_alloc(S, per * 0 + (size_t)S->chunk * N * N * N * tsz, &s);
     if (!S->X) { state_free(S); return s; }
     ALLOC(G, double, (size_t)S->chunk * 3 * N * N);
-    // cells of a pass left to a second expansion launch (oblique faces or
-    // ranks beyond the small LDS layout)
-    // two lists of a pass's cells and their counters (the oblique expansion
-    // hands cells on twice)
+    // cells of a pass left to later expansion launches (ranks beyond the
+    // small LDS layout, oblique sources beyond the one-stage budgets): two
+    // lists and their counters, since the oblique expansion hands cells on twice
     ALLOC(ob_list, int, 2 * (size_t)S->chunk);
     ALLOC(ob_n, int, 2);
     if (!S->mixed) ALLOC(Wb, double, (size_t)S->chunk * 3 * N * N);
@@ -823,11 +822,15 @@ static tk_status state_step_faces(tk_state* st) {
   if (e != hipSuccess) return ctx_hip(ctx, e, "moments");
   const int nc = st->nc, N = st->N, CS = st->CS;
   const int mx = st->mixed ? 1 : 0;
+  // face slot l's buffers
+  auto fcore = [&](int l) { return st->d_face_core + (size_t)l * nc * CS * CS * CS; };
+  auto ffac = [&](int l) { return st->d_face_fac + (size_t)l * nc * 3 * CS * N; };
+  auto frank = [&](int l) { return st->d_face_rank + (size_t)l * nc * 3; };
   FaceStates fs;
   for (int l = 0; l < kSlots; ++l) {
-    fs.core[l] = st->d_face_core + (size_t)l * nc * CS * CS * CS;
-    fs.fac[l] = st->d_face_fac + (size_t)l * nc * 3 * CS * N;
-    fs.rank[l] = st->d_face_rank + (size_t)l * nc * 3;
+    fs.core[l] = fcore(l);
+    fs.fac[l] = ffac(l);
+    fs.rank[l] = frank(l);
   }
   auto round_into = [&](int c0, int cnt, double* fac_o, int* rank_o, double* core_o) -> tk_status {
     prof_begin(ctx, KID_GRAM, &ev);
@@ -861,8 +864,7 @@ static tk_status state_step_faces(tk_state* st) {
       e = launch_face_term(d, c0, cnt, st->X, mx, l, q);
       prof_end(ctx, KID_EXPAND, ev);
       if (e != hipSuccess) return ctx_hip(ctx, e, "face term");
-      s = round_into(c0, cnt, const_cast<double*>(fs.fac[l]), const_cast<int*>(fs.rank[l]),
-                     const_cast<double*>(fs.core[l]));
+      s = round_into(c0, cnt, ffac(l), frank(l), fcore(l));
     }
     if (s != TK_OK) break;
     prof_begin(ctx, KID_EXPAND, &ev);

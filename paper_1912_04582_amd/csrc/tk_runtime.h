@@ -83,8 +83,8 @@ struct tk_state {
   // rounding workspaces
   void* X = nullptr;
   double* G = nullptr;
-  int* ob_list = nullptr;  // cells of a pass left to a second expansion launch
-  int* ob_n = nullptr;
+  int* ob_list = nullptr;  // [2][chunk] cells of a pass left to later expansion launches
+  int* ob_n = nullptr;     // [2] their counts
   // second workspace and stream: odd passes of a step run there, so one
   // pass's eigensolves overlap the next pass's expansion (allocated only
   // when the budget leaves room; not used while timing kernels or capturing)
