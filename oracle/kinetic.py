@@ -82,7 +82,7 @@ def maxwell_rank1(n, u, T, xi, Rg=0.5):
 
 
 def macros_tucker(t, xi, dxi, Rg=0.5, m=1.0):
-    """Macroparameters of a Tucker tensor by Op5 convolutions (Alg. 2 steps)."""
+    """Macroparameters of a Tucker tensor by Op5 convolutions (Alg. 2)."""
     w = dxi ** 3
     one = np.ones_like(xi)
     W = lambda a, v: [v if b == a else one for b in range(3)]  # noqa: E731

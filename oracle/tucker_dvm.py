@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY.
 
 Per cell, following the tensorised method (Section "Tensorized discrete
 velocity method"):
-  1. macroparameters by Op5 convolutions (Alg. 2 steps 1-9);
+  1. macroparameters by Op5 convolutions (Alg. 2, its moment part);
   2. f_S directly in Tucker form (rank 4 per mode);
   3. boundary ghosts in Tucker form (rank-1 Maxwellians, the cell itself,
      the cell with one factor's rows reversed, the scaled wall Maxwellian);

@@ -1,7 +1,7 @@
 // Macroparameters of every cell from its Tucker state, plus the wall ghost
 // densities, and the rank-1 Maxwellian initial state.
 //
-// Moments (Alg. 2 steps 1-9) are Op5 convolutions: per mode the factor
+// Moments (Alg. 2, its moment part) are Op5 convolutions: per mode the factor
 // columns are summed against 1-D weights (1, xi, xi^2 and the central
 // powers (xi - u_a)^p, p <= 3), then the core is contracted with those
 // sums.  T uses central second moments (equal to Alg. 2's raw form in

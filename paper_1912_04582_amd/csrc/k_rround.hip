@@ -4,7 +4,7 @@
 // assembly of one explicit step, one workgroup of four wavefronts per cell.
 //
 // The update f* = f + dt R of a cell on axis-aligned faces is a sum of
-// Tucker terms (eq. exact-flux in gather form, Alg. 1 steps 2-9; Op2 sums,
+// Tucker terms (eq. exact-flux in gather form, Alg. 1, the flux part; Op2 sums,
 // Op3 products with rank-1 row scalings):
 //
 //   f* = (1 - dt nu) f + sum_a d_a o_a f + dt nu f_S + sum_l b_l o_{a_l} g_l,
@@ -12,7 +12,7 @@
 //   b_l(i) = (dt A_l / V) max(-s_l xi_i, 0),
 //
 // where o_a scales the rows of mode a, f_S is the rank-4 S-model
-// equilibrium (Alg. 2 steps 10-11, Proposition 1) and g_l the far side of
+// equilibrium (Alg. 2, Proposition 1) and g_l the far side of
 // face l (neighbour state or boundary ghost).  Per mode a the factor of the
 // sum is the concatenation Ucat_a = [U_a, d_a U_a, F_a, far sides] with
 // r0_a = 2 r_a + 4 + sum_l q_l,a columns; its core is block-sparse.
