@@ -853,6 +853,19 @@ def main():
     fam, (fms, fn) = max(res["prof"].items(), key=lambda kv: kv[1][0])
     roof = roofline(fam, cfg, mesh, res, res["prof_steps"])
     log(f"  roofline ({fam}): {roof}")
+    # every family against its own bound, with the HBM rate its counted
+    # bytes (copy-calibrated counters, null once its source changed) give
+    kernel_roofs = {}
+    for f in res["prof"]:
+        r = roofline(f, cfg, mesh, res, res["prof_steps"])
+        if r is None:
+            continue
+        if r["traffic"] is not None:
+            r["hbm_gbps"] = r["traffic"] / (r["avg_launch_ms"] / 1e3) / 1e9
+            r["hbm_frac"] = r["hbm_gbps"] * 1e9 / PEAK["hbm"]
+        kernel_roofs[f] = r
+        log(f"  {f:10s} {r['achieved']:.3g} {r['unit']} ({r['frac']:.3f} of {r['peak']:.4g}, {r['bound']})"
+            + (f", HBM {r['hbm_gbps']:.0f} GB/s ({r['hbm_frac']:.3f})" if "hbm_gbps" in r else ""))
     plain = None
     if not a.no_plain:
         pres = run_gpu(cfg, mesh, m0, a.plain_steps, a.plain_steps, 1, plain=True)
@@ -927,6 +940,7 @@ def main():
         "rounding_paths_per_step": {k: v / window for k, v in (res["rounding_paths"] or {}).items()},
         "mean_compression": res["compression"],
         "roofline": roof,
+        "kernel_rooflines": kernel_roofs,
         "plain_gpu": plain,
         "fp64_path": fp64,
         "cpu_baseline": cpu,
