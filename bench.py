@@ -14,8 +14,8 @@ per-kernel events; `--steps 20` times steps 180-200, where the ranks are
 highest.
 
 One JSON line on stdout: metric/value (cell-updates/s over the timed
-window); per-kernel times and the roofline of the dominant kernel family
-from five further steps with every pass on one stream and HIP events around
+window); per-kernel times, the roofline of the dominant kernel family and
+of every other family (with its HBM rate) from five further steps with every pass on one stream and HIP events around
 each launch; the plain full-tensor GPU step on the same workload; the FP64
 path timed on the same window and the mixed path's end-of-run macro error
 against it, beside the FP64 path's own spread under a 1e-7 input
