@@ -293,9 +293,11 @@ tk_status tk_lusgs(tk_state* st, int32_t iters, double* residual);
  * to the instance's relative accuracy and rank cap on its own, then rounds
  * the sum (1 - dt nu) f + dt nu f_S + sum_l E~_l once more.  With eps -> 0
  * this is the exact update that on = 0 (the default) rounds once; otherwise
- * the two differ by at most eps (sum_l |E_l| + |f*|) per cell.  Every cell
- * takes the N-basis path, eagerly on the context stream (no graph replay,
- * no pass-size trials), with the precision's eigensolver (FP64: two passes).
+ * the result lies within eps (sum_l |E_l| (1 + eps) + |f*|) of the exact
+ * update f* per cell (Frobenius norms).  tk_lusgs iterations keep their own
+ * single rounding whatever the setting.  Every cell takes the N-basis path,
+ * eagerly on the context stream (no graph replay, no pass-size trials),
+ * with the precision's eigensolver (FP64: two passes).
  * The first enable allocates six state-sized buffers (TK_ENOMEM beyond the
  * budget); they live as long as the state.  TK_EINVAL for plain states and
  * a server's states.                                                      */
