@@ -44,6 +44,68 @@ namespace {
 
 constexpr int kEigThreads = 256;
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Warm-start rotation A <- V^T G V (G held in A) on the FP64 matrix cores:
+// Tm = G V, then the blocks on or above the diagonal of V^T Tm, mirrored so
+// that A stays exactly symmetric.  Each of the four wavefronts takes whole
+// 16x16 output blocks, accumulated with v_mfma_f64_16x16x4f64 over k (lane
+// (ii, kk) feeds row ii / column ii of the operands at k0 + kk and holds
+// rows kk + 4r of column ii of the result).  Rows and columns beyond N read
+// as zero and are not written; N is a multiple of 4.
+template <int N, int LD>
+__device__ void warm_rotate(double* A, const double* V, double* Tm) {
+  static_assert(N % 4 == 0, "k steps of 4");
+  constexpr int NB = (N + 15) / 16;
+  const int wave = threadIdx.x >> 6;
+  const int ii = threadIdx.x & 15, kk = (threadIdx.x >> 4) & 3;
+  for (int t = wave; t < NB * NB; t += kEigThreads / 64) {
+    const int bi = t / NB, bj = t % NB;
+    const int row = 16 * bi + ii, col = 16 * bj + ii;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < N; k0 += 4) {
+      const int k = k0 + kk;
+      const double a = row < N ? A[row * LD + k] : 0.0;
+      const double b = col < N ? V[k * LD + col] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * bi + kk + 4 * r;
+      if (i < N && col < N) Tm[i * LD + col] = acc[r];
+    }
+  }
+  __syncthreads();
+  for (int t = wave; t < NB * (NB + 1) / 2; t += kEigThreads / 64) {
+    // upper block t: row of blocks bi, column bj >= bi
+    int bi = 0, rest = t;
+    while (rest >= NB - bi) {
+      rest -= NB - bi;
+      ++bi;
+    }
+    const int bj = bi + rest;
+    const int row = 16 * bi + ii, col = 16 * bj + ii;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < N; k0 += 4) {
+      const int k = k0 + kk;
+      const double a = row < N ? V[k * LD + row] : 0.0;
+      const double b = col < N ? Tm[k * LD + col] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * bi + kk + 4 * r;
+      if (i < N && col < N && (bi != bj || i <= col)) {
+        A[i * LD + col] = acc[r];
+        A[col * LD + i] = acc[r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 }  // namespace
 
 // Eigensolver statistics: [1] matrices solved, [2] Jacobi sweeps run ([0]
@@ -53,7 +115,7 @@ __device__ unsigned long long g_eig_stats[4];
 namespace {
 
 template <int N>
-__global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
+__global__ __launch_bounds__(kEigThreads) __attribute__((amdgpu_waves_per_eu(N >= 48 ? 2 : 6))) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
                                                      int c0, double tol_o, int cap_o, int CS, double* fac_n,
                                                      int* rank_n, const double* Win, double* Wout, double* Wkeep,
                                                      double rel_thr, double abs_fac, double drop,
@@ -125,25 +187,8 @@ __global__ __launch_bounds__(kEigThreads, 6) void k_eig(const double* Gm, const 
   // the eigenvalue gap across the cut (far below the budget), and turns the
   // smallest kept directions by at most 1e-2 radian
   const double abs_thr = thr > 0.0 ? fmin(abs_fac * fabs(tot), 1e-2 * thr) : abs_fac * fabs(tot);
-  if (wr) {
-    // ---- full warm start: A <- V^T G V through Tm = G V --------------------
-    for (int o = lane; o < N * N; o += NT) {
-      const int i = o / N, j = o % N;
-      double s = 0.0;
-      for (int t = 0; t < N; ++t) s += A[i * LD + t] * V[t * LD + j];
-      Tm[i * LD + j] = s;
-    }
-    __syncthreads();
-    for (int o = lane; o < N * N; o += NT) {
-      const int i = o / N, j = o % N;
-      if (j < i) continue;
-      double s = 0.0;
-      for (int t = 0; t < N; ++t) s += V[t * LD + i] * Tm[t * LD + j];
-      A[i * LD + j] = s;
-      A[j * LD + i] = s;
-    }
-    __syncthreads();
-  }
+  // full warm start: A <- V^T G V
+  if (wr) warm_rotate<N, LD>(A, V, Tm);
   if (lane == 0) atomicAdd(&g_eig_stats[1], 1ull);
   jacobi<NT, NH>(A, LD, V, LD, N, N, rel_thr, abs_thr, cs, sn, tt, pp, qq, flag, &s_conv, &g_eig_stats[2]);
   sort_desc<NT>(A, LD + 1, N, order);
