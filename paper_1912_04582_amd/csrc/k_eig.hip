@@ -21,8 +21,9 @@
 //
 // Warm start: a cell's Gram changes little from one time step to the next,
 // so the full eigenbasis of the previous step is kept per cell and mode
-// (`Wkeep`); the matrix is first rotated into it (A = W^T G W, V = W) and
-// Jacobi then only removes the small off-diagonal remainder.  Rounds in
+// (`Wkeep`); the matrix is first rotated into it (A = W^T G W, V = W, two
+// N x N products on the FP64 matrix cores) and Jacobi then only removes the
+// small off-diagonal remainder.  Rounds in
 // which no pair needs a rotation skip the update passes; convergence is
 // checked by a parallel scan of the off-diagonal elements before each sweep.
 //
@@ -104,6 +105,36 @@ __device__ void warm_rotate(double* A, const double* V, double* Tm) {
     }
   }
   __syncthreads();
+}
+
+// The truncation rule on one wavefront (all 64 lanes call it, n <= 64):
+// lane k reads the k-th largest eigenvalue, the discarded tail is summed
+// from the smallest one upward in the same order as a serial loop, its
+// terms broadcast from the lanes' registers, so the result is bitwise that
+// of the serial rule.  Returns the rank r >= 1, capped.
+__device__ int choose_rank_wave(const double* lam, int stride, const int* order, int n, double thr, double drop,
+                                int cap) {
+  const int wl = threadIdx.x & 63;
+  const double lk = wl < n ? lam[order[wl] * stride] : 0.0;
+  int r = n;
+  if (drop > 0.0) {
+    const double l0 = __shfl(lk, 0, 64);
+    r = __popcll(__ballot(wl < n && lk > drop * drop * l0));
+  } else if (!(0.0 > thr)) {  // a negative budget keeps every vector
+    double tail = 0.0;
+    for (int k = n - 1; k >= 1; --k) {
+      const int lo = __builtin_amdgcn_readlane(__double2loint(lk), k);
+      const int hi = __builtin_amdgcn_readlane(__double2hiint(lk), k);
+      tail += __hiloint2double(hi, lo);
+      if (tail <= thr)
+        r = k;
+      else
+        break;
+    }
+  }
+  if (r > cap) r = cap;
+  if (r < 1) r = 1;
+  return r;
 }
 
 }  // namespace
@@ -216,46 +247,48 @@ __global__ __launch_bounds__(kEigThreads) __attribute__((amdgpu_waves_per_eu(N >
     }
     return;
   }
-  if (lane == 0) {
-    const int r = choose_rank(A, LD + 1, order, N, 0.0, thr, drop, cap);
-    s_rank = r;
-    rank_n[3 * cell + mode] = r;
+  if (lane < 64) {
+    const int r = choose_rank_wave(A, LD + 1, order, N, thr, drop, cap);
+    if (lane == 0) {
+      s_rank = r;
+      rank_n[3 * cell + mode] = r;
+    }
   }
   __syncthreads();
   const int r = s_rank;
+  // one wavefront per output column: the kept vectors (premultiplied by Win
+  // when given) with their canonical sign, largest-magnitude entry positive
+  // (the first on ties; a NaN entry never counts as largest), then zeros
   double* out = fac_n + ((size_t)cell * 3 + mode) * CS * N;
-  double* vec = Tm;
-  for (int c = 0; c < CS; ++c) {
+  const int wl = lane & 63;
+  for (int c = lane >> 6; c < CS; c += NT / 64) {
     if (c < r) {
       const int j = order[c];
-      for (int i = lane; i < N; i += NT) {
-        double v;
+      double v = 0.0;
+      if (wl < N) {
         if (Win) {
           const double* w = Win + (size_t)m * N * N;
-          v = 0.0;
-          for (int t = 0; t < N; ++t) v += w[t * N + i] * V[t * LD + j];
+          for (int t = 0; t < N; ++t) v += w[t * N + wl] * V[t * LD + j];
         } else {
-          v = V[i * LD + j];
+          v = V[wl * LD + j];
         }
-        vec[i] = v;
       }
-      __syncthreads();
-      // canonical sign: largest-magnitude entry positive (first on ties)
-      if (lane == 0) {
-        double best = -1.0;
-        int bi = 0;
-        for (int i = 0; i < N; ++i) {
-          const double v = fabs(vec[i]);
-          if (v > best) { best = v; bi = i; }
+      const double av = fabs(v);
+      double key = (wl < N && av == av) ? av : -1.0;
+      int idx = wl;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ok = __shfl_xor(key, off, 64);
+        const int oi = __shfl_xor(idx, off, 64);
+        if (ok > key || (ok == key && oi < idx)) {
+          key = ok;
+          idx = oi;
         }
-        cs[0] = (vec[bi] < 0.0) ? -1.0 : 1.0;
       }
-      __syncthreads();
-      const double sg = cs[0];
-      for (int i = lane; i < N; i += NT) out[c * N + i] = sg * vec[i];
-      __syncthreads();
-    } else {
-      for (int i = lane; i < N; i += NT) out[c * N + i] = 0.0;
+      const double sg = (__shfl(v, idx, 64) < 0.0) ? -1.0 : 1.0;
+      if (wl < N) out[c * N + wl] = sg * v;
+    } else if (wl < N) {
+      out[c * N + wl] = 0.0;
     }
   }
 }
