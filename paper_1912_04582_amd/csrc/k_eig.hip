@@ -47,39 +47,31 @@ constexpr int kEigThreads = 256;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Warm-start rotation A <- V^T G V (G held in A) on the FP64 matrix cores:
-// Tm = G V, then the blocks on or above the diagonal of V^T Tm, mirrored so
-// that A stays exactly symmetric.  Each of the four wavefronts takes whole
-// 16x16 output blocks, accumulated with v_mfma_f64_16x16x4f64 over k (lane
-// (ii, kk) feeds row ii / column ii of the operands at k0 + kk and holds
-// rows kk + 4r of column ii of the result).  Rows and columns beyond N read
-// as zero and are not written; N is a multiple of 4.
+// Warm-start rotation A <- V^T G V (G held in A) on the FP64 matrix cores,
+// v_mfma_f64_16x16x4f64 on 16x16 blocks: lane (ii, kk) feeds row ii /
+// column ii of the operands at k0 + kk and holds rows kk + 4r of column ii
+// of the result.  Each wavefront takes blocks (bi, bj >= bi) of the result:
+// it first forms column block bj of T = G V in registers, whose layout is
+// that of the second product's right operand (rows 16b + 4r + kk, column
+// ii), then accumulates V^T T over those rows.  The results are written
+// after every wavefront has read G, mirrored so that A stays exactly
+// symmetric.  Rows and columns beyond N read as zero and are not written;
+// N is a multiple of 4.
 template <int N, int LD>
-__device__ void warm_rotate(double* A, const double* V, double* Tm) {
+__device__ void warm_rotate(double* A, const double* V) {
   static_assert(N % 4 == 0, "k steps of 4");
   constexpr int NB = (N + 15) / 16;
+  constexpr int NU = NB * (NB + 1) / 2;
+  constexpr int NW = kEigThreads / 64;
+  constexpr int MT = (NU + NW - 1) / NW;
   const int wave = threadIdx.x >> 6;
   const int ii = threadIdx.x & 15, kk = (threadIdx.x >> 4) & 3;
-  for (int t = wave; t < NB * NB; t += kEigThreads / 64) {
-    const int bi = t / NB, bj = t % NB;
-    const int row = 16 * bi + ii, col = 16 * bj + ii;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int k0 = 0; k0 < N; k0 += 4) {
-      const int k = k0 + kk;
-      const double a = row < N ? A[row * LD + k] : 0.0;
-      const double b = col < N ? V[k * LD + col] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
+  v4d res[MT];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * bi + kk + 4 * r;
-      if (i < N && col < N) Tm[i * LD + col] = acc[r];
-    }
-  }
-  __syncthreads();
-  for (int t = wave; t < NB * (NB + 1) / 2; t += kEigThreads / 64) {
-    // upper block t: row of blocks bi, column bj >= bi
+  for (int u = 0; u < MT; ++u) {
+    const int t = wave + u * NW;
+    res[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (t >= NU) continue;
     int bi = 0, rest = t;
     while (rest >= NB - bi) {
       rest -= NB - bi;
@@ -87,20 +79,50 @@ __device__ void warm_rotate(double* A, const double* V, double* Tm) {
     }
     const int bj = bi + rest;
     const int row = 16 * bi + ii, col = 16 * bj + ii;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    v4d tm[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int gr = 16 * b + ii;
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-    for (int k0 = 0; k0 < N; k0 += 4) {
-      const int k = k0 + kk;
-      const double a = row < N ? V[k * LD + row] : 0.0;
-      const double b = col < N ? Tm[k * LD + col] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      for (int k0 = 0; k0 < N; k0 += 4) {
+        const int k = k0 + kk;
+        const double a = gr < N ? A[gr * LD + k] : 0.0;
+        const double v = col < N ? V[k * LD + col] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, v, acc, 0, 0, 0);
+      }
+      tm[b] = acc;
     }
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (16 * b + 4 * r >= N) continue;
+        const int k = 16 * b + 4 * r + kk;
+        const double a = row < N ? V[k * LD + row] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, tm[b][r], acc, 0, 0, 0);
+      }
+    res[u] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < MT; ++u) {
+    const int t = wave + u * NW;
+    if (t >= NU) continue;
+    int bi = 0, rest = t;
+    while (rest >= NB - bi) {
+      rest -= NB - bi;
+      ++bi;
+    }
+    const int bj = bi + rest;
+    const int col = 16 * bj + ii;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * bi + kk + 4 * r;
       if (i < N && col < N && (bi != bj || i <= col)) {
-        A[i * LD + col] = acc[r];
-        A[col * LD + i] = acc[r];
+        A[i * LD + col] = res[u][r];
+        A[col * LD + i] = res[u][r];
       }
     }
   }
@@ -145,8 +167,10 @@ __device__ unsigned long long g_eig_stats[4];
 
 namespace {
 
+// LDS holds the matrix and the basis (2 N (N + 1) doubles): seven
+// workgroups per CU at N = 32 within the register limit, four at N = 48.
 template <int N>
-__global__ __launch_bounds__(kEigThreads) __attribute__((amdgpu_waves_per_eu(N >= 48 ? 2 : 6))) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
+__global__ __launch_bounds__(kEigThreads) __attribute__((amdgpu_waves_per_eu(N >= 48 ? 4 : 6))) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
                                                      int c0, double tol_o, int cap_o, int CS, double* fac_n,
                                                      int* rank_n, const double* Win, double* Wout, double* Wkeep,
                                                      double rel_thr, double abs_fac, double drop,
@@ -156,7 +180,6 @@ __global__ __launch_bounds__(kEigThreads) __attribute__((amdgpu_waves_per_eu(N >
   constexpr int NH = N / 2;
   __shared__ double A[N * LD];
   __shared__ double V[N * LD];
-  __shared__ double Tm[N * LD];
   __shared__ double cs[NH], sn[NH], tt[NH];
   __shared__ int pp[NH], qq[NH];
   __shared__ int order[N];
@@ -219,7 +242,7 @@ __global__ __launch_bounds__(kEigThreads) __attribute__((amdgpu_waves_per_eu(N >
   // smallest kept directions by at most 1e-2 radian
   const double abs_thr = thr > 0.0 ? fmin(abs_fac * fabs(tot), 1e-2 * thr) : abs_fac * fabs(tot);
   // full warm start: A <- V^T G V
-  if (wr) warm_rotate<N, LD>(A, V, Tm);
+  if (wr) warm_rotate<N, LD>(A, V);
   if (lane == 0) atomicAdd(&g_eig_stats[1], 1ull);
   jacobi<NT, NH>(A, LD, V, LD, N, N, rel_thr, abs_thr, cs, sn, tt, pp, qq, flag, &s_conv, &g_eig_stats[2]);
   sort_desc<NT>(A, LD + 1, N, order);
