@@ -168,10 +168,10 @@ __device__ unsigned long long g_eig_stats[4];
 namespace {
 
 // LDS holds the matrix and the basis (2 N (N + 1) doubles): eight
-// workgroups per CU at N = 32 (64 registers, a few spilled), four at
-// N = 48.
+// workgroups per CU up to N = 32 (64 registers; two spilled at N = 32),
+// four at N = 48.
 template <int N>
-__global__ __launch_bounds__(kEigThreads) __attribute__((amdgpu_waves_per_eu(N >= 48 ? 4 : (N == 32 ? 8 : 6)))) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
+__global__ __launch_bounds__(kEigThreads) __attribute__((amdgpu_waves_per_eu(N >= 48 ? 4 : 8))) void k_eig(const double* Gm, const int* inst, const InstParams* ip,
                                                      int c0, double tol_o, int cap_o, int CS, double* fac_n,
                                                      int* rank_n, const double* Win, double* Wout, double* Wkeep,
                                                      double rel_thr, double abs_fac, double drop,
